@@ -1,0 +1,306 @@
+#!/usr/bin/env python3
+"""Benchmark of the BOBA hot path on one MI355X.
+
+A step is one pass of the whole path over one graph already resident in HBM:
+    boba_reorder -> boba_relabel -> coo_to_csr -> spmv_csr
+Warm-up steps are untimed; then exactly --steps steps are timed between two
+device synchronisations.  Every kernel of the library is also bracketed by HIP
+events on its launch stream (the torch current stream), which gives per-kernel
+durations for the roofline figures.
+
+Printed: one JSON line (stdout).  ``value`` is BOBA reorder throughput in edges
+per second (m / mean duration of boba_reorder inside the timed steps); the
+line also carries the whole-step time, SpMV GFLOP/s before (input labels) and
+after the reorder, per-kernel durations and HBM fractions, the roofline of the
+dominant kernel and the single-threaded CPU oracle timed on a bounded sample.
+Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "BOBA reorder edges/s + % HBM peak; SpMV GFLOP/s before vs after reorder"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_alg_bytes(name, n, m):
+    """Algorithmic bytes per launch: what the kernel must read and write at
+    minimum given its inputs and outputs (int32 / float32 = 4 bytes)."""
+    table = {
+        "scatter_min": 8 * m + 4 * n,          # read src, dst; write r once
+        "relabel": 16 * m + 4 * n,             # read src, dst, perm once; write both
+        "radix_scatter": 24 * m,               # read key, col, val; write them
+        "spmv": 8 * m + 4 * (n + 1) + 8 * n,   # val, col, rowptr, x once, y
+        "rank": 12 * n,                        # read r, write perm, order
+        "mark": 4 * n,                         # read r (bitmap writes are ours)
+    }
+    return table.get(name)
+
+
+def cpu_info():
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def source_digest():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2306_10410_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_traffic(kernel, workload, launches_per_step):
+    """HBM bytes per launch from a committed rocprofv3 PMC summary, if it was
+    taken on the current kernel sources; otherwise None."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_digest") != source_digest():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(g, budget_s):
+    """Single-threaded sequential oracle (Algorithm 1 + tail) on a prefix of
+    the edge list sized to roughly budget_s seconds."""
+    import numpy as np
+    import oracle
+
+    probe = min(g.m, 1 << 21)
+    t = time.perf_counter()
+    oracle.boba(g.src[:probe], g.dst[:probe], g.n)
+    rate = probe / max(time.perf_counter() - t, 1e-9)
+    sample = int(min(g.m, max(probe, rate * budget_s)))
+    s, d = np.ascontiguousarray(g.src[:sample]), np.ascontiguousarray(g.dst[:sample])
+    t = time.perf_counter()
+    oracle.boba(s, d, g.n)
+    el = time.perf_counter() - t
+    what = "whole edge list" if sample == g.m else f"first {sample} of {g.m} edges (all n = {g.n} vertices)"
+    return {"value": sample / el, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"sequential BOBA (C, -O2, 1 thread) on {what}; {el:.2f} s",
+            "cpu_model": cpu_info()[0], "host_cpus": cpu_info()[1]}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rmat24", help="rmat24 | rmat20 | grid4096 | uniform14")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of CPU oracle work (0: skip)")
+    ap.add_argument("--before-reps", type=int, default=5)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        log("multi-GPU runs are not part of this build (one GPU per box); exiting")
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_2306_10410_amd import boba, graphgen
+
+    if not torch.cuda.is_available():
+        log("no HIP device visible")
+        return 1
+    boba.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    log(f"generating {args.workload}")
+    t0 = time.perf_counter()
+    g = graphgen.make_workload(args.workload)
+    n, m = g.n, g.m
+    log(f"n={n} m={m} generated in {time.perf_counter() - t0:.1f}s; uploading")
+    src = torch.from_numpy(g.src).to(dev)
+    dst = torch.from_numpy(g.dst).to(dev)
+    val = torch.from_numpy(g.val).to(dev)
+    x = torch.from_numpy(g.x).to(dev)
+
+    perm = torch.empty(n, dtype=torch.int32, device=dev)
+    order = torch.empty(n, dtype=torch.int32, device=dev)
+    s2 = torch.empty(m, dtype=torch.int32, device=dev)
+    d2 = torch.empty(m, dtype=torch.int32, device=dev)
+    ws_r = torch.empty(boba.boba_reorder_workspace(n, m), dtype=torch.uint8, device=dev)
+    ws_c = torch.empty(boba.coo_to_csr_workspace(n, m), dtype=torch.uint8, device=dev)
+    rowptr = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    col = torch.empty(m, dtype=torch.int32, device=dev)
+    val_c = torch.empty(m, dtype=torch.float32, device=dev)
+    y = torch.empty(n, dtype=torch.float32, device=dev)
+    x2 = torch.empty(n, dtype=torch.float32, device=dev)
+
+    stage_names = ["reorder", "relabel", "coo_to_csr", "spmv"]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+
+    def step(e=None):
+        if e:
+            e[0].record()
+        boba.boba_reorder(src, dst, n, ws=ws_r, perm=perm, order=order)
+        if e:
+            e[1].record()
+        boba.boba_relabel(src, dst, perm, src_out=s2, dst_out=d2)
+        if e:
+            e[2].record()
+        boba.coo_to_csr(s2, d2, val, n, ws=ws_c, out=(rowptr, col, val_c))
+        if e:
+            e[3].record()
+        boba.spmv_csr(rowptr, col, val_c, x2, y=y)
+        if e:
+            e[4].record()
+
+    # x in the new labelling, so the reordered product equals the original one
+    boba.boba_reorder(src, dst, n, ws=ws_r, perm=perm, order=order)
+    x2[perm.long()] = x
+    log(f"warmup {args.warmup} steps")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    assert boba.boba_check_device_error() == boba.BOBA_OK
+
+    boba.boba_timing_enable(True)
+    boba.boba_timing_collect()
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(ev[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern = boba.boba_timing_collect()
+    boba.boba_timing_enable(False)
+    stage_ms = {name: float(np.mean([ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(args.steps)]))
+                for i, name in enumerate(stage_names)}
+    ms_per_step = wall * 1e3 / args.steps
+    log(f"{ms_per_step:.3f} ms/step; stages {stage_ms}")
+
+    # SpMV and CSR build on the input labelling ("before")
+    log("before-reorder leg")
+    rp0 = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    col0 = torch.empty(m, dtype=torch.int32, device=dev)
+    val0 = torch.empty(m, dtype=torch.float32, device=dev)
+    y0 = torch.empty(n, dtype=torch.float32, device=dev)
+    b_csr, b_spmv = [], []
+    for _ in range(args.before_reps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        boba.coo_to_csr(src, dst, val, n, ws=ws_c, out=(rp0, col0, val0))
+        e[1].record()
+        boba.spmv_csr(rp0, col0, val0, x, y=y0)
+        e[2].record()
+        torch.cuda.synchronize()
+        b_csr.append(e[0].elapsed_time(e[1]))
+        b_spmv.append(e[1].elapsed_time(e[2]))
+    before_csr_ms, before_spmv_ms = float(np.median(b_csr)), float(np.median(b_spmv))
+    # the reordered SpMV must reproduce the input-order one
+    yb = y0.cpu().numpy().astype(np.float64)
+    ya = y.cpu().numpy().astype(np.float64)[perm.cpu().numpy()]
+    spmv_agree = float(np.linalg.norm(ya - yb) / max(np.linalg.norm(yb), 1e-30))
+    assert boba.boba_check_device_error() == boba.BOBA_OK
+
+    kernels = {}
+    for name, (tot, cnt) in kern.items():
+        per_step = cnt / args.steps
+        avg = tot / cnt
+        entry = {"avg_ms": avg, "launches_per_step": per_step, "ms_per_step": tot / args.steps}
+        ab = kernel_alg_bytes(name, n, m)
+        if ab is not None:
+            entry["alg_bytes_per_launch"] = ab
+            entry["achieved_GBs"] = ab / (avg * 1e-3) / 1e9
+            entry["hbm_frac"] = entry["achieved_GBs"] / HBM_PEAK_GBS
+        kernels[name] = entry
+    dom = max((k for k in kernels if "alg_bytes_per_launch" in kernels[k]),
+              key=lambda k: kernels[k]["ms_per_step"])
+    dk = kernels[dom]
+    traffic = pmc_traffic(dom, args.workload, dk["launches_per_step"])
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["achieved_GBs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": dk["achieved_GBs"] / HBM_PEAK_GBS, "traffic": traffic,
+                "alg_bytes_per_launch": dk["alg_bytes_per_launch"], "avg_ms": dk["avg_ms"]}
+
+    reorder_ms = stage_ms["reorder"]
+    reorder_alg = 8 * m + 16 * n  # read I, J; write and read r; write perm and order
+    cpu = None
+    if args.cpu_budget > 0:
+        log("CPU oracle baseline")
+        cpu = cpu_baseline(g, args.cpu_budget)
+
+    out = {
+        "metric": METRIC,
+        "value": m / (reorder_ms * 1e-3),
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "m": m,
+                   "generator": _describe(args.workload),
+                   "step": "boba_reorder -> boba_relabel -> coo_to_csr -> spmv_csr"},
+        "reorder_ms": reorder_ms,
+        "reorder_hbm_frac_alg": reorder_alg / (reorder_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "path_edges_per_s": m / (ms_per_step * 1e-3),
+        "stages_ms": stage_ms,
+        "spmv_gflops_before": 2 * m / (before_spmv_ms * 1e-3) / 1e9,
+        "spmv_gflops_after": 2 * m / (stage_ms["spmv"] * 1e-3) / 1e9,
+        "spmv_dtype": "f32",
+        "coo_to_csr_ms_before": before_csr_ms,
+        "coo_to_csr_ms_after": stage_ms["coo_to_csr"],
+        "spmv_reordered_vs_input_rel_l2": spmv_agree,
+        "kernels": kernels,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "device": torch.cuda.get_device_name(0),
+        "source_digest": source_digest(),
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def _describe(workload):
+    return {
+        "rmat24": "RMAT(0.57,0.19,0.19,0.05) scale 24, edge factor 16, random labels; FP32 val, x ~ U(-1,1)",
+        "rmat20": "RMAT(0.57,0.19,0.19,0.05) scale 20, edge factor 16, random labels; FP32 val, x ~ U(-1,1)",
+        "grid4096": "4096x4096 4-neighbour mesh, random labels, edge order kept; FP32 val, x ~ U(-1,1)",
+        "uniform14": "n=16384, m=131072 uniform endpoints, random labels; FP32 val, x ~ U(-1,1)",
+    }.get(workload, workload)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,134 @@
+/*
+ * boba.h -- C ABI of libboba.so, an MI355X (gfx950) implementation of the
+ * data-parallel hot path of BOBA (Batched Order By Attachment, arXiv
+ * 2306.10410): first-occurrence reorder -> edge relabel -> COO->CSR -> SpMV.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Array arguments are DEVICE pointers (hipMalloc'd or equivalent), owned by
+ *    the caller; the library keeps no reference after the call returns.
+ *    Exceptions are marked "host".
+ *  - Calls are asynchronous on `stream` (0 = the null stream): they enqueue
+ *    kernels and return.  Outputs are valid once the stream reaches that point.
+ *  - Vertex IDs are int32 in [0, n); edge counts m and vertex counts n must be
+ *    < 2^31.  BOBA positions are uint32, so boba_reorder also needs 2m + n < 2^32.
+ *  - Host-detectable errors (null pointers, negative or oversized sizes, a
+ *    workspace that is too small) are returned before anything is enqueued.
+ *  - Every kernel that indexes memory by a vertex ID bounds-checks it.  An
+ *    out-of-range ID is skipped and recorded in a per-device flag; read and
+ *    clear it with boba_check_device_error.  Results are unspecified then.
+ *  - Results are deterministic: bit-identical across runs, launch shapes and
+ *    tuning choices.
+ *  - boba_last_error() returns a thread-local description of the last failure.
+ */
+#ifndef BOBA_H
+#define BOBA_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#ifndef BOBA_API
+#define BOBA_API __attribute__((visibility("default")))
+#endif
+
+typedef int32_t boba_status;
+#define BOBA_OK 0
+#define BOBA_ERR_ARG 1       /* null pointer, negative size, bad flag */
+#define BOBA_ERR_RANGE 2     /* a vertex ID outside [0, n) (device-detected) */
+#define BOBA_ERR_OVERFLOW 3  /* m or n >= 2^31, or 2m + n >= 2^32 */
+#define BOBA_ERR_WORKSPACE 4 /* workspace null or smaller than the query said */
+#define BOBA_ERR_HIP 5       /* a HIP runtime call or kernel launch failed */
+
+/* boba_reorder flags */
+#define BOBA_FLAG_INTERLEAVED 0x1u /* flatten as I(0) J(0) I(1) J(1) ... (Fig. 1)
+                                      instead of I ++ J (Algorithms 1 and 2) */
+
+/* Thread-local, NUL-terminated description of the most recent failure on this
+ * thread ("" if none).  The string stays valid until the next call. */
+BOBA_API const char *boba_last_error(void);
+
+/* Waits for `stream`, then reports whether any kernel on the current device saw
+ * a vertex ID out of range since the last check (*code = BOBA_ERR_RANGE) or not
+ * (*code = BOBA_OK), and clears the flag.  `code` is a host pointer. */
+BOBA_API boba_status boba_check_device_error(hipStream_t stream, int32_t *code);
+
+/* ------------------------------------------------------------- reorder ---
+ * BOBA reordering (Sec. 4.4, Algorithm 2 with AtomicMin, which the paper notes
+ * reproduces Algorithm 1 of Sec. 4.3 exactly).  With S = I ++ J (positions
+ * 0..2m-1; I = src, J = dst) followed by the tail 0..n-1 (positions 2m..2m+n-1,
+ * so vertices that never occur come last, in increasing old ID):
+ *     first(v) = min { i : S[i] = v }
+ *     perm[v]  = #{ u : first(u) < first(v) }       (new ID of old vertex v)
+ *     order[k] = v  such that perm[v] = k           (the paper's permutation p)
+ * i.e. vertices are numbered in order of first appearance.
+ *   src, dst  int32[m]  edge list (COO); m may be 0 (then src/dst may be NULL).
+ *   perm      int32[n]  output, required.
+ *   order     int32[n]  output, may be NULL.
+ *   ws        workspace of at least boba_reorder_workspace(n, m) bytes,
+ *             256-byte aligned; contents on entry are ignored.
+ *   flags     0 or BOBA_FLAG_INTERLEAVED.
+ * Errors: BOBA_ERR_ARG, BOBA_ERR_OVERFLOW, BOBA_ERR_WORKSPACE, BOBA_ERR_HIP. */
+BOBA_API size_t boba_reorder_workspace(int64_t n, int64_t m);
+BOBA_API boba_status boba_reorder(const int32_t *src, const int32_t *dst, int64_t m, int64_t n,
+                         int32_t *perm, int32_t *order, void *ws, size_t ws_bytes,
+                         uint32_t flags, hipStream_t stream);
+
+/* ------------------------------------------------------------- relabel ---
+ * Applies a vertex permutation to an edge list (the step between BOBA and CSR
+ * construction, Sec. 5.3): src_out[k] = perm[src[k]], dst_out[k] = perm[dst[k]].
+ * Edge order is unchanged.  In place is allowed (src_out == src and/or
+ * dst_out == dst); other overlaps are not.
+ *   src, dst, src_out, dst_out  int32[m];  perm  int32[n].
+ * Errors: BOBA_ERR_ARG, BOBA_ERR_OVERFLOW, BOBA_ERR_HIP. */
+BOBA_API boba_status boba_relabel(const int32_t *src, const int32_t *dst, int64_t m,
+                         const int32_t *perm, int64_t n, int32_t *src_out, int32_t *dst_out,
+                         hipStream_t stream);
+
+/* ---------------------------------------------------------- COO -> CSR ---
+ * Builds CSR from COO (the conversion of Sec. 1.1 and Sec. 5.3) by a stable
+ * sort on the row: rowptr[r] = #{k : row[k] < r}, and within each row the
+ * entries keep their input order k.  Duplicates and self-loops are kept.
+ *   row, col  int32[m];  val  float[m] or NULL.
+ *   rowptr    int32[n_rows + 1] output;  col_out int32[m];  val_out float[m]
+ *             (NULL exactly when val is NULL).  Outputs must not alias inputs.
+ *   ws        at least coo_to_csr_workspace(n_rows, m) bytes, 256-byte aligned.
+ * Errors: BOBA_ERR_ARG, BOBA_ERR_OVERFLOW, BOBA_ERR_WORKSPACE, BOBA_ERR_HIP. */
+BOBA_API size_t coo_to_csr_workspace(int64_t n_rows, int64_t m);
+BOBA_API boba_status coo_to_csr(const int32_t *row, const int32_t *col, const float *val, int64_t m,
+                       int64_t n_rows, int32_t *rowptr, int32_t *col_out, float *val_out,
+                       void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------- SpMV ---
+ * y = A x for CSR A (Algorithm 3, SpMV; rows of CSR as in Sec. 1.2):
+ *     y[r] = sum_{e in [rowptr[r], rowptr[r+1])} val[e] * x[col[e]]
+ * in FP32.  val may be NULL (all ones).
+ *   rowptr int32[n_rows+1], col int32[nnz], val float[nnz], x float[n_cols],
+ *   y float[n_rows] (must not alias x).  rowptr must be a valid offset array
+ *   (rowptr[0] = 0, non-decreasing, rowptr[n_rows] = nnz); it is not checked,
+ *   column indices are.
+ * Errors: BOBA_ERR_ARG, BOBA_ERR_OVERFLOW, BOBA_ERR_HIP. */
+BOBA_API boba_status spmv_csr(const int32_t *rowptr, const int32_t *col, const float *val,
+                     int64_t n_rows, int64_t n_cols, const float *x, float *y,
+                     hipStream_t stream);
+
+/* -------------------------------------------------------------- timing ---
+ * Per-kernel timing with HIP events, for benchmarks (off by default).  While
+ * enabled, every kernel the library launches outside stream capture is
+ * bracketed by a pair of events recorded on its stream. */
+BOBA_API boba_status boba_timing_enable(int32_t on);
+/* Waits for every recorded event, then writes up to max_entries entries: the
+ * kernel names packed NUL-terminated into names_buf (host, buf_len bytes),
+ * total_ms[k] (host) the summed durations and launches[k] (host) the launch
+ * counts since the last collect.  Clears the records; returns the entry count. */
+BOBA_API int32_t boba_timing_collect(char *names_buf, size_t buf_len, double *total_ms, int64_t *launches,
+                                     int32_t max_entries);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BOBA_H */

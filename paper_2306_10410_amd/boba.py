@@ -1,0 +1,172 @@
+"""Python binding of libboba.so: argument marshalling only.
+
+Every function here has the name of the C entry point it calls (include/boba.h)
+and takes torch tensors that live on the current HIP device; all work runs in
+the library's kernels on the current torch stream (or ``stream``).  PyTorch
+provides device memory and streams, nothing else.  If libboba.so is missing the
+first call raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libboba.so")
+
+BOBA_OK, BOBA_ERR_ARG, BOBA_ERR_RANGE, BOBA_ERR_OVERFLOW, BOBA_ERR_WORKSPACE, BOBA_ERR_HIP = range(6)
+BOBA_FLAG_INTERLEAVED = 0x1
+_STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_RANGE", 3: "ERR_OVERFLOW", 4: "ERR_WORKSPACE", 5: "ERR_HIP"}
+
+# name -> (restype, argtypes); the exact C prototypes of include/boba.h
+_P, _I64, _U32, _I32, _SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_size_t
+PROTOTYPES = {
+    "boba_last_error": (ctypes.c_char_p, []),
+    "boba_check_device_error": (_I32, [_P, _P]),
+    "boba_reorder_workspace": (_SZ, [_I64, _I64]),
+    "boba_reorder": (_I32, [_P, _P, _I64, _I64, _P, _P, _P, _SZ, _U32, _P]),
+    "boba_relabel": (_I32, [_P, _P, _I64, _P, _I64, _P, _P, _P]),
+    "coo_to_csr_workspace": (_SZ, [_I64, _I64]),
+    "coo_to_csr": (_I32, [_P, _P, _P, _I64, _I64, _P, _P, _P, _P, _SZ, _P]),
+    "spmv_csr": (_I32, [_P, _P, _P, _I64, _I64, _P, _P, _P]),
+    "boba_timing_enable": (_I32, [_I32]),
+    "boba_timing_collect": (_I32, [_P, _SZ, _P, _P, _I32]),
+}
+
+_lib = None
+
+
+class BobaError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def load():
+    """Load libboba.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2306_10410_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in PROTOTYPES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != BOBA_OK:
+        raise BobaError(status, load().boba_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_i32(t, name):
+    if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous int32 device tensor")
+    return t
+
+
+def _workspace(nbytes: int, device, ws=None):
+    if ws is not None and ws.numel() >= nbytes:
+        return ws
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+
+
+def boba_reorder_workspace(n: int, m: int) -> int:
+    return int(load().boba_reorder_workspace(n, m))
+
+
+def boba_reorder(src, dst, n: int, *, with_order: bool = True, flags: int = 0, ws=None, perm=None,
+                 order=None, stream=None):
+    """Returns (perm, order) as int32 device tensors: perm[old] = new,
+    order[new] = old (order is None unless with_order)."""
+    _dev_i32(src, "src")
+    _dev_i32(dst, "dst")
+    m = src.numel()
+    if dst.numel() != m:
+        raise ValueError("src and dst differ in length")
+    dev = src.device
+    perm = torch.empty(n, dtype=torch.int32, device=dev) if perm is None else perm
+    if with_order and order is None:
+        order = torch.empty(n, dtype=torch.int32, device=dev)
+    need = boba_reorder_workspace(n, m)
+    ws = _workspace(need, dev, ws)
+    _check(load().boba_reorder(_ptr(src), _ptr(dst), m, n, _ptr(perm), _ptr(order) if with_order else None,
+                               _ptr(ws), ws.numel(), flags, _stream(stream)))
+    return perm, (order if with_order else None)
+
+
+def boba_relabel(src, dst, perm, *, src_out=None, dst_out=None, stream=None):
+    _dev_i32(src, "src")
+    _dev_i32(dst, "dst")
+    _dev_i32(perm, "perm")
+    src_out = torch.empty_like(src) if src_out is None else src_out
+    dst_out = torch.empty_like(dst) if dst_out is None else dst_out
+    _check(load().boba_relabel(_ptr(src), _ptr(dst), src.numel(), _ptr(perm), perm.numel(), _ptr(src_out),
+                               _ptr(dst_out), _stream(stream)))
+    return src_out, dst_out
+
+
+def coo_to_csr_workspace(n_rows: int, m: int) -> int:
+    return int(load().coo_to_csr_workspace(n_rows, m))
+
+
+def coo_to_csr(row, col, val, n_rows: int, *, ws=None, out=None, stream=None):
+    """Returns (rowptr[n_rows+1], col_out, val_out or None)."""
+    _dev_i32(row, "row")
+    _dev_i32(col, "col")
+    m = row.numel()
+    dev = row.device
+    if out is None:
+        rowptr = torch.empty(n_rows + 1, dtype=torch.int32, device=dev)
+        col_out = torch.empty(m, dtype=torch.int32, device=dev)
+        val_out = None if val is None else torch.empty(m, dtype=torch.float32, device=dev)
+    else:
+        rowptr, col_out, val_out = out
+    ws = _workspace(coo_to_csr_workspace(n_rows, m), dev, ws)
+    _check(load().coo_to_csr(_ptr(row), _ptr(col), _ptr(val), m, n_rows, _ptr(rowptr), _ptr(col_out),
+                             _ptr(val_out), _ptr(ws), ws.numel(), _stream(stream)))
+    return rowptr, col_out, val_out
+
+
+def spmv_csr(rowptr, col, val, x, *, y=None, stream=None):
+    _dev_i32(rowptr, "rowptr")
+    _dev_i32(col, "col")
+    n_rows = rowptr.numel() - 1
+    y = torch.empty(n_rows, dtype=torch.float32, device=x.device) if y is None else y
+    _check(load().spmv_csr(_ptr(rowptr), _ptr(col), _ptr(val), n_rows, x.numel(), _ptr(x), _ptr(y),
+                           _stream(stream)))
+    return y
+
+
+def boba_check_device_error(stream=None) -> int:
+    code = ctypes.c_int32(0)
+    _check(load().boba_check_device_error(_stream(stream), ctypes.byref(code)))
+    return int(code.value)
+
+
+def boba_timing_enable(on: bool = True):
+    _check(load().boba_timing_enable(1 if on else 0))
+
+
+def boba_timing_collect(max_entries: int = 64):
+    """Returns {kernel name: (total ms, launches)} since the last collect."""
+    buf = ctypes.create_string_buffer(64 * max_entries)
+    ms = (ctypes.c_double * max_entries)()
+    cnt = (ctypes.c_int64 * max_entries)()
+    k = load().boba_timing_collect(buf, len(buf), ms, cnt, max_entries)
+    names = buf.raw.split(b"\0")[:k]
+    return {names[i].decode(): (ms[i], cnt[i]) for i in range(k)}

@@ -1,0 +1,264 @@
+// COO -> CSR by a stable least-significant-digit radix sort on the row
+// (the conversion step of Sec. 1.1 / Sec. 5.3, moved from the CPU to the GPU).
+//
+// Per digit pass:
+//   hist     per 4096-edge tile, a histogram of the digit (LDS atomics),
+//            stored digit-major: hist[d * tiles + t]
+//   scan     exclusive scan of hist -> where tile t's digit-d run starts
+//   scatter  stable rank inside the tile (wave ballots + per-wave LDS
+//            counters, waves own contiguous 1024-edge runs), local sort in
+//            LDS, then coalesced writes of key / col / val runs
+// After the last pass rowptr comes from the sorted rows: the end of each row's
+// run is written at rowptr[row + 1], then an inclusive max-scan fills rows
+// without entries.
+#include "internal.h"
+#include "scan.h"
+
+namespace boba {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kNWave = kBlock / kWave;
+constexpr int kItems = 16;
+constexpr uint32_t kTile = kBlock * kItems;       // edges per workgroup
+constexpr uint32_t kWaveRun = kWave * kItems;     // contiguous edges per wave
+
+template <int BITS>
+__global__ __launch_bounds__(kBlock) void k_radix_hist(const int32_t *__restrict__ keys, uint32_t m, uint32_t shift,
+                                                       uint32_t tiles, uint32_t *__restrict__ hist) {
+    constexpr uint32_t BINS = 1u << BITS;
+    __shared__ uint32_t h[BINS];
+    for (uint32_t d = threadIdx.x; d < BINS; d += kBlock) h[d] = 0;
+    __syncthreads();
+    const uint32_t base = blockIdx.x * kTile + threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        uint32_t i = base + j * kBlock;
+        if (i < m) atomicAdd(&h[((uint32_t)keys[i] >> shift) & (BINS - 1)], 1u);
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < BINS; d += kBlock) hist[d * tiles + blockIdx.x] = h[d];
+}
+
+template <int BITS, bool HAS_VAL>
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(const int32_t *__restrict__ keys_in,
+                                                          const int32_t *__restrict__ col_in,
+                                                          const float *__restrict__ val_in, uint32_t m,
+                                                          uint32_t shift, uint32_t tiles,
+                                                          const uint32_t *__restrict__ offs,
+                                                          int32_t *__restrict__ keys_out,
+                                                          int32_t *__restrict__ col_out,
+                                                          float *__restrict__ val_out) {
+    constexpr uint32_t BINS = 1u << BITS;
+    constexpr uint32_t MASK = BINS - 1;
+    constexpr uint32_t DPT = BINS / kBlock;  // digits per thread in the tile scan
+    static_assert(BINS % kBlock == 0, "need at least 8 digit bits");
+    __shared__ uint32_t s_cnt[kNWave][BINS];  // per-wave counts, then run starts
+    __shared__ uint32_t s_gofs[BINS];
+    __shared__ uint32_t s_start[BINS];
+    __shared__ uint32_t s_scan[kNWave];
+    __shared__ int32_t s_key[kTile];
+    __shared__ int32_t s_col[kTile];
+    __shared__ float s_val[HAS_VAL ? kTile : 1];
+
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wave = threadIdx.x / kWave;
+    for (uint32_t i = threadIdx.x; i < kNWave * BINS; i += kBlock) (&s_cnt[0][0])[i] = 0;
+    for (uint32_t d = threadIdx.x; d < BINS; d += kBlock) s_gofs[d] = offs[d * tiles + blockIdx.x];
+    __syncthreads();
+
+    const uint32_t tile_base = blockIdx.x * kTile;
+    const uint32_t wbase = tile_base + wave * kWaveRun;
+    const uint64_t lt_mask = (1ull << lane) - 1ull;
+    int32_t key[kItems], col[kItems];
+    float val[kItems];
+    uint32_t rank[kItems];
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        const uint32_t i = wbase + j * kWave + lane;
+        const bool valid = i < m;
+        key[j] = valid ? keys_in[i] : 0;
+        col[j] = valid ? col_in[i] : 0;
+        if (HAS_VAL) val[j] = valid ? val_in[i] : 0.f;
+        const uint32_t d = ((uint32_t)key[j] >> shift) & MASK;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < BITS; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            peers &= bit ? bb : ~bb;
+        }
+        const uint32_t below = __popcll(peers & lt_mask);
+        const uint32_t prior = s_cnt[wave][d];
+        if (valid && below == 0) s_cnt[wave][d] = prior + (uint32_t)__popcll(peers);
+        rank[j] = prior + below;
+    }
+    __syncthreads();
+
+    // Tile-local start of every (digit, wave) run, digit-major.
+    {
+        uint32_t s = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < DPT; ++q) {
+            const uint32_t d = threadIdx.x * DPT + q;
+#pragma unroll
+            for (int w = 0; w < kNWave; ++w) s += s_cnt[w][d];
+        }
+        uint32_t total;
+        uint32_t run = block_exclusive_scan<kBlock>(s, OpSum{}, s_scan, total);
+#pragma unroll
+        for (uint32_t q = 0; q < DPT; ++q) {
+            const uint32_t d = threadIdx.x * DPT + q;
+            s_start[d] = run;
+#pragma unroll
+            for (int w = 0; w < kNWave; ++w) {
+                const uint32_t c = s_cnt[w][d];
+                s_cnt[w][d] = run;
+                run += c;
+            }
+        }
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        const uint32_t i = wbase + j * kWave + lane;
+        if (i < m) {
+            const uint32_t d = ((uint32_t)key[j] >> shift) & MASK;
+            const uint32_t p = s_cnt[wave][d] + rank[j];
+            s_key[p] = key[j];
+            s_col[p] = col[j];
+            if (HAS_VAL) s_val[p] = val[j];
+        }
+    }
+    __syncthreads();
+
+    const uint32_t count = m - tile_base < kTile ? m - tile_base : kTile;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        const uint32_t p = j * kBlock + threadIdx.x;
+        if (p < count) {
+            const int32_t k = s_key[p];
+            const uint32_t d = ((uint32_t)k >> shift) & MASK;
+            const uint32_t g = s_gofs[d] + (p - s_start[d]);
+            if (g >= m) continue;  // unreachable when the offsets are consistent
+            keys_out[g] = k;
+            col_out[g] = s_col[p];
+            if (HAS_VAL) val_out[g] = s_val[p];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *__restrict__ a, uint32_t count, uint32_t v) {
+    const uint32_t stride = gridDim.x * kBlock;
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) a[i] = v;
+}
+
+// rowptr[row + 1] <- end of row's run in the sorted keys.
+__global__ __launch_bounds__(kBlock) void k_row_ends(const int32_t *__restrict__ keys, uint32_t m, uint32_t n_rows,
+                                                     uint32_t *__restrict__ rowptr, int32_t *flag) {
+    const uint32_t stride = gridDim.x * kBlock;
+    for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < m; k += stride) {
+        const int32_t key = keys[k];
+        if ((uint32_t)key >= n_rows) {
+            flag_range_error(flag);
+            continue;
+        }
+        if (k + 1 == m || keys[k + 1] != key) rowptr[key + 1] = k + 1;
+    }
+}
+
+constexpr int kBits = 8;
+
+struct CsrLayout {
+    int32_t *keys_a, *keys_b, *col_x;
+    float *val_x;
+    uint32_t *hist, *partial;
+    size_t bytes;
+    uint32_t tiles;
+};
+
+CsrLayout csr_layout(void *ws, int64_t n_rows, int64_t m, bool has_val) {
+    CsrLayout L;
+    L.tiles = ceil_div((uint64_t)m, kTile);
+    const uint64_t hist_count = (uint64_t)(1u << kBits) * L.tiles;
+    const uint64_t scan_count = hist_count > (uint64_t)n_rows + 1 ? hist_count : (uint64_t)n_rows + 1;
+    Carver c(ws);
+    L.keys_a = c.take<int32_t>((size_t)m);
+    L.keys_b = c.take<int32_t>((size_t)m);
+    L.col_x = c.take<int32_t>((size_t)m);
+    L.val_x = c.take<float>(has_val ? (size_t)m : 0);
+    L.hist = c.take<uint32_t>((size_t)hist_count);
+    L.partial = c.take<uint32_t>(scan_partials(scan_count));
+    L.bytes = c.bytes();
+    return L;
+}
+
+}  // namespace
+}  // namespace boba
+
+using namespace boba;
+
+extern "C" size_t coo_to_csr_workspace(int64_t n_rows, int64_t m) {
+    if (n_rows < 0 || m < 0) return 0;
+    return csr_layout(nullptr, n_rows, m, true).bytes;
+}
+
+extern "C" boba_status coo_to_csr(const int32_t *row, const int32_t *col, const float *val, int64_t m,
+                                  int64_t n_rows, int32_t *rowptr, int32_t *col_out, float *val_out, void *ws,
+                                  size_t ws_bytes, hipStream_t stream) {
+    clear_error();
+    if (m < 0 || n_rows < 0) return fail(BOBA_ERR_ARG, "coo_to_csr: negative size");
+    if (m >= (1ll << 31) || n_rows >= (1ll << 31)) return fail(BOBA_ERR_OVERFLOW, "coo_to_csr: m and n_rows must be < 2^31");
+    if (!rowptr) return fail(BOBA_ERR_ARG, "coo_to_csr: rowptr is NULL");
+    if ((val == nullptr) != (val_out == nullptr))
+        return fail(BOBA_ERR_ARG, "coo_to_csr: val and val_out must both be given or both be NULL");
+    if (m > 0 && (!row || !col || !col_out)) return fail(BOBA_ERR_ARG, "coo_to_csr: NULL pointer");
+    if (m > 0 && n_rows == 0) return fail(BOBA_ERR_ARG, "coo_to_csr: edges given but n_rows = 0");
+    const size_t need = coo_to_csr_workspace(n_rows, m);
+    if (!ws || ws_bytes < need || ((uintptr_t)ws & 255u))
+        return fail(BOBA_ERR_WORKSPACE, "coo_to_csr: workspace needs %zu bytes, 256-byte aligned (got %zu at %p)",
+                    need, ws_bytes, ws);
+    int32_t *flag = range_flag();
+    if (!flag) return BOBA_ERR_HIP;
+    const bool has_val = val != nullptr;
+    CsrLayout L = csr_layout(ws, n_rows, m, has_val);
+    const uint32_t um = (uint32_t)m, nr = (uint32_t)n_rows;
+
+    BOBA_LAUNCH("csr_fill", k_fill_u32, dim3(grid_for(nr + 1ull, kBlock * 4)), dim3(kBlock), stream,
+                (uint32_t *)rowptr, nr + 1, 0u);
+    if (m == 0) return BOBA_OK;
+
+    uint32_t bits = 0;
+    while (bits < 31 && (1ull << bits) < (uint64_t)nr) ++bits;
+    const int passes = bits == 0 ? 1 : (int)((bits + kBits - 1) / kBits);
+    const uint32_t hist_count = (1u << kBits) * L.tiles;
+
+    const int32_t *kin = row;
+    const int32_t *cin = col;
+    const float *vin = val;
+    for (int p = 0; p < passes; ++p) {
+        const uint32_t shift = (uint32_t)(p * kBits);
+        const bool to_out = ((passes - 1 - p) % 2) == 0;
+        int32_t *kout = (p % 2 == 0) ? L.keys_a : L.keys_b;
+        int32_t *cout = to_out ? col_out : L.col_x;
+        float *vout = to_out ? val_out : L.val_x;
+        BOBA_LAUNCH("radix_hist", k_radix_hist<kBits>, dim3(L.tiles), dim3(kBlock), stream, kin, um, shift, L.tiles,
+                    L.hist);
+        if (boba_status e = device_scan<OpSum, false>("radix_offsets", LoadArr{L.hist}, StoreArr{L.hist}, hist_count, L.partial, stream))
+            return e;
+        if (has_val)
+            BOBA_LAUNCH("radix_scatter", (k_radix_scatter<kBits, true>), dim3(L.tiles), dim3(kBlock), stream, kin, cin,
+                        vin, um, shift, L.tiles, (const uint32_t *)L.hist, kout, cout, vout);
+        else
+            BOBA_LAUNCH("radix_scatter", (k_radix_scatter<kBits, false>), dim3(L.tiles), dim3(kBlock), stream, kin, cin,
+                        vin, um, shift, L.tiles, (const uint32_t *)L.hist, kout, cout, vout);
+        kin = kout;
+        cin = cout;
+        vin = vout;
+    }
+    BOBA_LAUNCH("row_ends", k_row_ends, dim3(grid_for(um, kBlock * 4)), dim3(kBlock), stream, kin, um, nr,
+                (uint32_t *)rowptr, flag);
+    return device_scan<OpMax, true>("rowptr_scan", LoadArr{(const uint32_t *)rowptr}, StoreArr{(uint32_t *)rowptr}, nr + 1,
+                                    L.partial, stream);
+}

@@ -1,0 +1,119 @@
+"""The C-ABI boundary on the CPU: libboba.so loads, exports every entry point
+include/boba.h declares with the prototypes the binding uses, and rejects bad
+arguments on the host before anything is enqueued (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2306_10410_amd import boba
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", f) for f in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if f.endswith(".h")]
+
+
+def declared_functions():
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        text = re.sub(r"^\s*#[^\n]*", " ", text, flags=re.M)
+        for m in re.finditer(r"\b([A-Za-z_]\w*)\s*\(", text):
+            name = m.group(1)
+            start = text.rfind(";", 0, m.start())
+            decl = text[start + 1:m.start()]
+            if "typedef" in decl or name in ("extern", "if", "sizeof"):
+                continue
+            if re.search(r"\b(boba_status|size_t|const|char|void|int32_t|int64_t)\b", decl):
+                names.add(name)
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(boba.LIB_PATH):
+        from paper_2306_10410_amd import build
+        build.build()
+    return boba.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert {"boba_reorder", "boba_relabel", "coo_to_csr", "spmv_csr"} <= names
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in include/ but not exported"
+    assert names == set(boba.PROTOTYPES), "binding prototypes and header disagree"
+
+
+def test_workspace_queries_are_host_only(lib):
+    assert boba.boba_reorder_workspace(0, 0) >= 0
+    small = boba.boba_reorder_workspace(16384, 131072)
+    big = boba.boba_reorder_workspace(1 << 24, 1 << 28)
+    # r (4n) + bitmap words (8 bytes per 32 positions) dominate
+    assert big >= 4 * (1 << 24) + 8 * ((2 * (1 << 28) + (1 << 24)) // 32)
+    assert small < big
+    assert lib.boba_reorder_workspace(-1, 5) == 0
+    assert boba.coo_to_csr_workspace(1 << 20, 1 << 24) >= 3 * 4 * (1 << 24)
+
+
+P = ctypes.c_void_p
+FAKE = P(0x10000)  # never dereferenced: every call below fails validation first
+
+
+def status_and_msg(lib, rc):
+    return rc, lib.boba_last_error().decode()
+
+
+def test_reorder_argument_errors(lib):
+    ws_need = lib.boba_reorder_workspace(10, 10)
+    cases = [
+        ((FAKE, FAKE, -1, 10, FAKE, None, FAKE, ws_need, 0, None), boba.BOBA_ERR_ARG),
+        ((FAKE, FAKE, 10, -1, FAKE, None, FAKE, ws_need, 0, None), boba.BOBA_ERR_ARG),
+        ((FAKE, FAKE, 1 << 31, 10, FAKE, None, FAKE, ws_need, 0, None), boba.BOBA_ERR_OVERFLOW),
+        ((FAKE, FAKE, 10, 1 << 31, FAKE, None, FAKE, ws_need, 0, None), boba.BOBA_ERR_OVERFLOW),
+        ((FAKE, FAKE, (1 << 31) - 1, (1 << 31) - 1, FAKE, None, FAKE, ws_need, 0, None), boba.BOBA_ERR_OVERFLOW),
+        ((None, FAKE, 10, 10, FAKE, None, FAKE, ws_need, 0, None), boba.BOBA_ERR_ARG),
+        ((FAKE, None, 10, 10, FAKE, None, FAKE, ws_need, 0, None), boba.BOBA_ERR_ARG),
+        ((FAKE, FAKE, 10, 10, None, None, FAKE, ws_need, 0, None), boba.BOBA_ERR_ARG),
+        ((FAKE, FAKE, 10, 10, FAKE, None, FAKE, ws_need, 0x80, None), boba.BOBA_ERR_ARG),
+        ((FAKE, FAKE, 10, 0, FAKE, None, FAKE, ws_need, 0, None), boba.BOBA_ERR_ARG),
+        ((FAKE, FAKE, 10, 10, FAKE, None, None, ws_need, 0, None), boba.BOBA_ERR_WORKSPACE),
+        ((FAKE, FAKE, 10, 10, FAKE, None, FAKE, ws_need - 1, 0, None), boba.BOBA_ERR_WORKSPACE),
+        ((FAKE, FAKE, 10, 10, FAKE, None, P(0x10004), ws_need, 0, None), boba.BOBA_ERR_WORKSPACE),
+    ]
+    for args, want in cases:
+        rc, msg = status_and_msg(lib, lib.boba_reorder(*args))
+        assert rc == want, (args, rc, msg)
+        assert msg, "an error must leave a message"
+    # nothing to do: OK without touching the device
+    assert lib.boba_reorder(None, None, 0, 0, None, None, None, 0, 0, None) == boba.BOBA_OK
+    assert lib.boba_last_error().decode() == ""
+
+
+def test_relabel_csr_spmv_argument_errors(lib):
+    assert lib.boba_relabel(FAKE, FAKE, -1, FAKE, 5, FAKE, FAKE, None) == boba.BOBA_ERR_ARG
+    assert lib.boba_relabel(FAKE, FAKE, 1 << 31, FAKE, 5, FAKE, FAKE, None) == boba.BOBA_ERR_OVERFLOW
+    assert lib.boba_relabel(FAKE, None, 3, FAKE, 5, FAKE, FAKE, None) == boba.BOBA_ERR_ARG
+    assert lib.boba_relabel(FAKE, FAKE, 3, None, 5, FAKE, FAKE, None) == boba.BOBA_ERR_ARG
+    assert lib.boba_relabel(None, None, 0, None, 0, None, None, None) == boba.BOBA_OK
+    need = lib.coo_to_csr_workspace(5, 3)
+    assert lib.coo_to_csr(FAKE, FAKE, FAKE, 3, 5, FAKE, FAKE, None, FAKE, need, None) == boba.BOBA_ERR_ARG
+    assert lib.coo_to_csr(FAKE, FAKE, None, 3, 5, None, FAKE, None, FAKE, need, None) == boba.BOBA_ERR_ARG
+    assert lib.coo_to_csr(FAKE, FAKE, None, 3, 5, FAKE, FAKE, None, FAKE, need - 1, None) == boba.BOBA_ERR_WORKSPACE
+    assert lib.coo_to_csr(FAKE, FAKE, None, 3, 0, FAKE, FAKE, None, FAKE, need, None) == boba.BOBA_ERR_ARG
+    assert lib.coo_to_csr(FAKE, FAKE, None, -3, 5, FAKE, FAKE, None, FAKE, need, None) == boba.BOBA_ERR_ARG
+    assert lib.spmv_csr(FAKE, FAKE, None, -1, 5, FAKE, FAKE, None) == boba.BOBA_ERR_ARG
+    assert lib.spmv_csr(None, FAKE, None, 4, 5, FAKE, FAKE, None) == boba.BOBA_ERR_ARG
+    assert lib.spmv_csr(FAKE, FAKE, None, 1 << 31, 5, FAKE, FAKE, None) == boba.BOBA_ERR_OVERFLOW
+    assert lib.spmv_csr(None, None, None, 0, 0, None, None, None) == boba.BOBA_OK
+    assert lib.boba_check_device_error(None, None) == boba.BOBA_ERR_ARG
+
+
+def test_binding_refuses_host_tensors():
+    import torch
+    x = torch.zeros(4, dtype=torch.int32)
+    with pytest.raises(TypeError):
+        boba.boba_reorder(x, x, 4)

@@ -1,0 +1,195 @@
+"""GPU parity: every step of the hot path through the C ABI against the CPU
+oracle on the same seeded inputs, element by element (bit-exact integers and
+CSR values; SpMV within 1e-5 relative L2 of FP64)."""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2306_10410_amd import boba, graphgen
+from gpu_util import SPMV_TOL, bits_equal, dev, full_path_check, host, rel_l2, requires_gpu
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+
+def encode(tokens, code):
+    return np.array([code[t] for t in tokens], np.int32)
+
+
+@pytest.mark.parametrize("interleaved", [False, True])
+def test_fig2_roads(golden, interleaved):
+    g = golden("fig2_roads.txt")
+    names = sorted(set(g["I"]) | set(g["J"]))
+    ids = np.random.default_rng(9).permutation(len(names))
+    code = {nm: int(ids[k]) for k, nm in enumerate(names)}
+    I, J = encode(g["I"], code), encode(g["J"], code)
+    flags = boba.BOBA_FLAG_INTERLEAVED if interleaved else 0
+    _, order = boba.boba_reorder(dev(I), dev(J), len(names), flags=flags)
+    inv = {v: k for k, v in code.items()}
+    assert [inv[int(v)] for v in host(order)] == g["order"]
+
+
+def test_fig1_star_both_flattenings(golden):
+    g = golden("fig1_star.txt")
+    names = sorted(set(g["I"]) | set(g["J"]), key=lambda s: (len(s), s))
+    code = {nm: k for k, nm in enumerate(names)}
+    I, J = encode(g["I"], code), encode(g["J"], code)
+    _, order = boba.boba_reorder(dev(I), dev(J), len(names), flags=boba.BOBA_FLAG_INTERLEAVED)
+    assert [names[v] for v in host(order)] == g["order_interleaved"]
+    _, order = boba.boba_reorder(dev(I), dev(J), len(names))
+    assert [names[v] for v in host(order)] == g["I"][:11] + ["a"]
+
+
+def test_brute_force_every_edge_order():
+    rng = np.random.default_rng(3)
+    for trial in range(4):
+        n = int(rng.integers(1, 6))
+        m = int(rng.integers(1, 6))
+        I0, J0 = rng.integers(0, n, m), rng.integers(0, n, m)
+        for p in itertools.permutations(range(m)):
+            I = I0[list(p)].astype(np.int32)
+            J = J0[list(p)].astype(np.int32)
+            for inter in (False, True):
+                perm, _ = boba.boba_reorder(dev(I), dev(J), n,
+                                            flags=boba.BOBA_FLAG_INTERLEAVED if inter else 0)
+                assert np.array_equal(host(perm), oracle.boba(I, J, n, inter)[0])
+
+
+@pytest.mark.parametrize("m", [0, 1, 2, 3, 4, 5, 7, 8, 63, 64, 65, 1023, 4095, 4096, 4097, 16385])
+def test_ragged_edge_counts(m):
+    g = graphgen.small_workload("uniform", 1000, m, 100 + m)
+    full_path_check(g, boba)
+    full_path_check(g, boba, interleaved=True, check_spmv=False)
+
+
+def test_degenerate_graphs():
+    # n = 1, only self-loops
+    g = graphgen.Graph("loop1", 1, np.zeros(9, np.int32), np.zeros(9, np.int32),
+                       np.ones(9, np.float32), np.ones(1, np.float32))
+    full_path_check(g, boba)
+    # all vertices isolated
+    g = graphgen.Graph("iso", 777, np.zeros(0, np.int32), np.zeros(0, np.int32),
+                       np.zeros(0, np.float32), graphgen.uniform_values(777, 5))
+    full_path_check(g, boba)
+    # only self-loops, many vertices, maximum ID present
+    v = np.array([999, 3, 500, 999, 0, 3], np.int32)
+    g = graphgen.Graph("loops", 1000, v, v.copy(), graphgen.uniform_values(6, 6), graphgen.uniform_values(1000, 7))
+    full_path_check(g, boba)
+    # a single hub: star listed with the centre as source
+    leaves = np.random.default_rng(8).permutation(np.arange(1, 5000)).astype(np.int32)
+    g = graphgen.Graph("star", 5000, np.zeros(leaves.size, np.int32), leaves,
+                       graphgen.uniform_values(leaves.size, 9), graphgen.uniform_values(5000, 10))
+    full_path_check(g, boba)
+
+
+@pytest.mark.parametrize("kind,n,m", [("uniform", 16384, 131072), ("rmat", 1 << 16, (1 << 20) + 3),
+                                      ("rgg", 50000, 400000), ("grid", 300 * 300, 0),
+                                      ("rmat", 100003, 1600037)])
+def test_random_graphs_full_path(kind, n, m):
+    g = graphgen.small_workload(kind, n, m, 7 + n)
+    full_path_check(g, boba)
+
+
+def test_uniform14_workload_full_path():
+    full_path_check(graphgen.make_workload("uniform14"), boba)
+
+
+def test_unaligned_inputs_take_the_scalar_path():
+    g = graphgen.small_workload("rmat", 4096, 40001, 77)
+    big_s = dev(np.concatenate([[0], g.src]).astype(np.int32))
+    big_d = dev(np.concatenate([[0], g.dst]).astype(np.int32))
+    s, d = big_s[1:], big_d[1:]
+    assert s.data_ptr() % 16 != 0
+    perm, order = boba.boba_reorder(s, d, g.n)
+    p_ref, o_ref = oracle.boba(g.src, g.dst, g.n)
+    assert np.array_equal(host(perm), p_ref) and np.array_equal(host(order), o_ref)
+    out_s = torch.empty(g.m + 1, dtype=torch.int32, device="cuda")[1:]
+    out_d = torch.empty(g.m + 1, dtype=torch.int32, device="cuda")[1:]
+    boba.boba_relabel(s, d, perm, src_out=out_s, dst_out=out_d)
+    s_ref, d_ref = oracle.relabel(g.src, g.dst, p_ref)
+    assert np.array_equal(host(out_s), s_ref) and np.array_equal(host(out_d), d_ref)
+
+
+def test_relabel_in_place():
+    g = graphgen.small_workload("rmat", 8192, 100000, 78)
+    s, d = dev(g.src), dev(g.dst)
+    perm, _ = boba.boba_reorder(s, d, g.n)
+    boba.boba_relabel(s, d, perm, src_out=s, dst_out=d)
+    s_ref, d_ref = oracle.relabel(g.src, g.dst, oracle.boba(g.src, g.dst, g.n)[0])
+    assert np.array_equal(host(s), s_ref) and np.array_equal(host(d), d_ref)
+
+
+def test_idempotence_on_gpu():
+    g = graphgen.small_workload("rgg", 20000, 160000, 79)
+    s, d = dev(g.src), dev(g.dst)
+    perm, _ = boba.boba_reorder(s, d, g.n)
+    s2, d2 = boba.boba_relabel(s, d, perm)
+    perm2, _ = boba.boba_reorder(s2, d2, g.n)
+    assert np.array_equal(host(perm2), np.arange(g.n))
+
+
+def test_csr_without_values_and_spmv_special_cases():
+    g = graphgen.small_workload("uniform", 3000, 30000, 80)
+    rowptr, col, val = boba.coo_to_csr(dev(g.src), dev(g.dst), None, g.n)
+    assert val is None
+    rp_ref, col_ref, _ = oracle.coo_to_csr(g.src, g.dst, None, g.n)
+    assert np.array_equal(host(rowptr), rp_ref) and np.array_equal(host(col), col_ref)
+    # all-ones values and x: y = out-degree exactly
+    y = boba.spmv_csr(rowptr, col, None, torch.ones(g.n, device="cuda"))
+    assert np.array_equal(host(y), np.diff(rp_ref).astype(np.float32))
+    # identity matrix: y = x bitwise
+    n = 5000
+    x = dev(graphgen.uniform_values(n, 81))
+    eye_rp = torch.arange(n + 1, dtype=torch.int32, device="cuda")
+    eye_col = torch.arange(n, dtype=torch.int32, device="cuda")
+    y = boba.spmv_csr(eye_rp, eye_col, torch.ones(n, device="cuda"), x)
+    assert bits_equal(host(y), host(x))
+
+
+def test_spmv_permutation_equivariance():
+    g = graphgen.small_workload("rmat", 1 << 14, 1 << 18, 82)
+    s, d = dev(g.src), dev(g.dst)
+    val = dev(g.val)
+    rp, col, v = boba.coo_to_csr(s, d, val, g.n)
+    y0 = host(boba.spmv_csr(rp, col, v, dev(g.x)))
+    perm, _ = boba.boba_reorder(s, d, g.n)
+    s2, d2 = boba.boba_relabel(s, d, perm)
+    rp2, col2, v2 = boba.coo_to_csr(s2, d2, val, g.n)
+    x2 = torch.empty_like(dev(g.x))
+    x2[perm.long()] = dev(g.x)
+    y1 = host(boba.spmv_csr(rp2, col2, v2, x2))
+    assert rel_l2(y1[host(perm)], y0) <= SPMV_TOL
+
+
+def test_deterministic_repeats():
+    g = graphgen.small_workload("rmat", 1 << 16, 1 << 20, 83)
+    s, d = dev(g.src), dev(g.dst)
+    ref = None
+    for _ in range(5):
+        perm, order = boba.boba_reorder(s, d, g.n)
+        rp, col, v = boba.coo_to_csr(s, d, dev(g.val), g.n)
+        y = boba.spmv_csr(rp, col, v, dev(g.x))
+        cur = [host(perm), host(order), host(rp), host(col), host(v).view(np.uint32), host(y).view(np.uint32)]
+        if ref is None:
+            ref = cur
+        for a, b in zip(ref, cur):
+            assert np.array_equal(a, b)
+
+
+def test_out_of_range_ids_set_the_device_flag():
+    assert boba.boba_check_device_error() == boba.BOBA_OK
+    s = dev(np.array([0, 1, 2, 3], np.int32))
+    d = dev(np.array([1, 2, 3, 9], np.int32))  # 9 >= n = 4: skipped by the kernels
+    boba.boba_reorder(s, d, 4)
+    assert boba.boba_check_device_error() == boba.BOBA_ERR_RANGE
+    assert boba.boba_check_device_error() == boba.BOBA_OK  # cleared
+    perm = dev(np.arange(4, dtype=np.int32))
+    boba.boba_relabel(s, d, perm)
+    assert boba.boba_check_device_error() == boba.BOBA_ERR_RANGE
+    boba.coo_to_csr(d, s, None, 4)
+    assert boba.boba_check_device_error() == boba.BOBA_ERR_RANGE
+    rp = dev(np.array([0, 2, 4], np.int32))
+    boba.spmv_csr(rp, d, None, torch.ones(4, device="cuda"))
+    assert boba.boba_check_device_error() == boba.BOBA_ERR_RANGE
