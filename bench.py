@@ -44,6 +44,8 @@ def kernel_alg_bytes(name, n, m):
         "relabel": 16 * m + 4 * n,             # read src, dst, perm once; write both
         "radix_scatter": 24 * m,               # read key, col, val; write them
         "spmv": 8 * m + 4 * (n + 1) + 8 * n,   # val, col, rowptr, x once, y
+        "bucket_split": 16 * m,                # read src, dst; write one record each
+        "bucket_min": 8 * m + 4 * n,           # read the records; write r
         "rank": 12 * n,                        # read r, write perm, order
         "mark": 4 * n,                         # read r (bitmap writes are ours)
     }
@@ -162,6 +164,7 @@ def main():
     val_c = torch.empty(m, dtype=torch.float32, device=dev)
     y = torch.empty(n, dtype=torch.float32, device=dev)
     x2 = torch.empty(n, dtype=torch.float32, device=dev)
+    ws_s = torch.empty(boba.spmv_csr_workspace(n, m), dtype=torch.uint8, device=dev)
 
     stage_names = ["reorder", "relabel", "coo_to_csr", "spmv"]
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
@@ -178,7 +181,7 @@ def main():
         boba.coo_to_csr(s2, d2, val, n, ws=ws_c, out=(rowptr, col, val_c))
         if e:
             e[3].record()
-        boba.spmv_csr(rowptr, col, val_c, x2, y=y)
+        boba.spmv_csr(rowptr, col, val_c, x2, y=y, ws=ws_s)
         if e:
             e[4].record()
 
@@ -219,7 +222,7 @@ def main():
         e[0].record()
         boba.coo_to_csr(src, dst, val, n, ws=ws_c, out=(rp0, col0, val0))
         e[1].record()
-        boba.spmv_csr(rp0, col0, val0, x, y=y0)
+        boba.spmv_csr(rp0, col0, val0, x, y=y0, ws=ws_s)
         e[2].record()
         torch.cuda.synchronize()
         b_csr.append(e[0].elapsed_time(e[1]))

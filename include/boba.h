@@ -106,15 +106,21 @@ BOBA_API boba_status coo_to_csr(const int32_t *row, const int32_t *col, const fl
 /* ---------------------------------------------------------------- SpMV ---
  * y = A x for CSR A (Algorithm 3, SpMV; rows of CSR as in Sec. 1.2):
  *     y[r] = sum_{e in [rowptr[r], rowptr[r+1])} val[e] * x[col[e]]
- * in FP32.  val may be NULL (all ones).
- *   rowptr int32[n_rows+1], col int32[nnz], val float[nnz], x float[n_cols],
- *   y float[n_rows] (must not alias x).  rowptr must be a valid offset array
- *   (rowptr[0] = 0, non-decreasing, rowptr[n_rows] = nnz); it is not checked,
- *   column indices are.
- * Errors: BOBA_ERR_ARG, BOBA_ERR_OVERFLOW, BOBA_ERR_HIP. */
+ * in FP32.  Work is split evenly over nonzeros, so very long rows cost no more
+ * than many short ones; every row is summed in a fixed order, so results are
+ * bit-reproducible.  val may be NULL (all ones).
+ *   rowptr int32[n_rows+1], col int32[nnz], val float[nnz] or NULL,
+ *   x float[n_cols], y float[n_rows] (must not alias x).  col and x may be
+ *   NULL when nnz = 0.  rowptr should satisfy rowptr[0] = 0, non-decreasing,
+ *   rowptr[n_rows] = nnz; offsets and row indices are clamped, so a malformed
+ *   rowptr gives wrong sums, never out-of-bounds accesses.  Column indices
+ *   outside [0, n_cols) are skipped and flagged.
+ *   ws  at least spmv_csr_workspace(n_rows, nnz) bytes, 256-byte aligned.
+ * Errors: BOBA_ERR_ARG, BOBA_ERR_OVERFLOW, BOBA_ERR_WORKSPACE, BOBA_ERR_HIP. */
+BOBA_API size_t spmv_csr_workspace(int64_t n_rows, int64_t nnz);
 BOBA_API boba_status spmv_csr(const int32_t *rowptr, const int32_t *col, const float *val,
-                     int64_t n_rows, int64_t n_cols, const float *x, float *y,
-                     hipStream_t stream);
+                              int64_t n_rows, int64_t n_cols, int64_t nnz, const float *x, float *y,
+                              void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* -------------------------------------------------------------- timing ---
  * Per-kernel timing with HIP events, for benchmarks (off by default).  While

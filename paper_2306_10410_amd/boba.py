@@ -30,7 +30,8 @@ PROTOTYPES = {
     "boba_relabel": (_I32, [_P, _P, _I64, _P, _I64, _P, _P, _P]),
     "coo_to_csr_workspace": (_SZ, [_I64, _I64]),
     "coo_to_csr": (_I32, [_P, _P, _P, _I64, _I64, _P, _P, _P, _P, _SZ, _P]),
-    "spmv_csr": (_I32, [_P, _P, _P, _I64, _I64, _P, _P, _P]),
+    "spmv_csr_workspace": (_SZ, [_I64, _I64]),
+    "spmv_csr": (_I32, [_P, _P, _P, _I64, _I64, _I64, _P, _P, _P, _SZ, _P]),
     "boba_timing_enable": (_I32, [_I32]),
     "boba_timing_collect": (_I32, [_P, _SZ, _P, _P, _I32]),
 }
@@ -142,13 +143,18 @@ def coo_to_csr(row, col, val, n_rows: int, *, ws=None, out=None, stream=None):
     return rowptr, col_out, val_out
 
 
-def spmv_csr(rowptr, col, val, x, *, y=None, stream=None):
+def spmv_csr_workspace(n_rows: int, nnz: int) -> int:
+    return int(load().spmv_csr_workspace(n_rows, nnz))
+
+
+def spmv_csr(rowptr, col, val, x, *, y=None, ws=None, stream=None):
     _dev_i32(rowptr, "rowptr")
     _dev_i32(col, "col")
     n_rows = rowptr.numel() - 1
     y = torch.empty(n_rows, dtype=torch.float32, device=x.device) if y is None else y
-    _check(load().spmv_csr(_ptr(rowptr), _ptr(col), _ptr(val), n_rows, x.numel(), _ptr(x), _ptr(y),
-                           _stream(stream)))
+    ws = _workspace(spmv_csr_workspace(n_rows, col.numel()), x.device, ws)
+    _check(load().spmv_csr(_ptr(rowptr), _ptr(col), _ptr(val), n_rows, x.numel(), col.numel(), _ptr(x), _ptr(y),
+                           _ptr(ws), ws.numel(), _stream(stream)))
     return y
 
 

@@ -4,6 +4,8 @@
 //   init      r[v] <- inf, bitmap <- 0
 //   scatter   for every position i of the flattened edge list S = I ++ J,
 //             r[S[i]] <- min(r[S[i]], i)          (Algorithm 2, lines with r)
+//             either directly (one global atomic min per new position) or,
+//             for graphs up to 2^25 vertices, bucketed through LDS (below)
 //   mark      key(v) = r[v], or 2m + v when v never occurs (tail); set bit
 //             key(v) in a bitmap over [0, 2m + n)
 //   scan      prefix popcount of the bitmap words      } ParMapKeys: the rank
@@ -208,24 +210,269 @@ __global__ __launch_bounds__(kBlock) void k_relabel_scalar(const int32_t *src, c
     }
 }
 
+
+// ------------------------------------------------------- bucketed scatter-min
+// The direct scatter above issues one random 4-byte read of r per position;
+// for a 64 MB r those reads run at HBM random-access speed.  The bucketed path
+// never touches r per position:
+//   split     each workgroup takes a tile of kTileT consecutive elements of
+//             one half (src or dst), groups them by vertex bucket
+//             v >> kVBits in LDS (counting sort, bucket segments padded to
+//             4 records) and writes the tile's records + segment offsets.
+//             A record packs (element offset in tile) << kVBits | (v mod W).
+//   transpose the per-tile offsets to bucket-major order.
+//   bucket    one workgroup per (bucket, slice of tiles) keeps the bucket's
+//             2^kVBits r values in LDS and folds every record in with an LDS
+//             atomic min; the slice's minima are written out coalesced.
+// Slices (several workgroups per bucket) keep the GPU busy when there are few
+// buckets; their partial minima are merged by the mark kernel.
+constexpr int kSplitThreads = 1024;
+constexpr int kSplitPer = 32;                                   // elements per thread
+constexpr uint32_t kTileT = kSplitThreads * kSplitPer;          // 32768 elements per tile
+constexpr int kVBits = 15;
+constexpr uint32_t kBucketW = 1u << kVBits;                     // vertices per bucket
+constexpr uint32_t kMaxBuckets = 1024;                          // LDS budget of split
+constexpr uint32_t kSentinel = 0xFFFFFFFFu;
+constexpr int kMinThreads = 1024;
+constexpr int kMinGroup = 8;                                    // tiles per wave step
+
+inline uint32_t split_region(uint32_t nb) { return (kTileT + 3 * nb + 3) & ~3u; }
+
+__global__ __launch_bounds__(kSplitThreads) void k_bucket_split(const int32_t *__restrict__ src,
+                                                                 const int32_t *__restrict__ dst, uint32_t m,
+                                                                 uint32_t tiles_half, uint32_t n, uint32_t nb,
+                                                                 uint32_t region, uint32_t *__restrict__ recs,
+                                                                 uint32_t *__restrict__ tile_off, int32_t *flag) {
+    __shared__ __align__(16) uint32_t stage[kTileT + 3 * kMaxBuckets];
+    __shared__ uint32_t hist[kMaxBuckets];
+    __shared__ uint32_t cur[kMaxBuckets];
+    __shared__ uint32_t scan_lds[kSplitThreads / kWave];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t t = blockIdx.x;
+    const bool h = t >= tiles_half;
+    const uint32_t k0 = (t - (h ? tiles_half : 0u)) * kTileT;
+    const int32_t *a = h ? dst : src;
+    for (uint32_t i = tid; i < nb; i += kSplitThreads) hist[i] = 0;
+    __syncthreads();
+
+    // element e = k0 + j*4096 + 4*tid + q: every load instruction is coalesced
+    int32_t v[kSplitPer];
+#pragma unroll
+    for (int j = 0; j < kSplitPer / 4; ++j) {
+        const uint32_t e = k0 + j * (4 * kSplitThreads) + 4 * tid;
+        if (e + 3 < m) {
+            const v4i x = __builtin_nontemporal_load((const v4i *)(a + e));
+            v[4 * j] = x.x;
+            v[4 * j + 1] = x.y;
+            v[4 * j + 2] = x.z;
+            v[4 * j + 3] = x.w;
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[4 * j + q] = e + q < m ? a[e + q] : -1;
+        }
+    }
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < kSplitPer / 4; ++j) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t e = k0 + j * (4 * kSplitThreads) + 4 * tid + q;
+            const int32_t x = v[4 * j + q];
+            if (e < m) {
+                if ((uint32_t)x < n) {
+                    atomicAdd(&hist[(uint32_t)x >> kVBits], 1u);
+                } else {
+                    bad = true;
+                    v[4 * j + q] = -1;
+                }
+            }
+        }
+    }
+    if (bad) flag_range_error(flag);
+    __syncthreads();
+
+    const uint32_t c = tid < nb ? hist[tid] : 0u;
+    const uint32_t pc = (c + 3) & ~3u;
+    uint32_t total;
+    const uint32_t start = block_exclusive_scan<kSplitThreads>(pc, OpSum{}, scan_lds, total);
+    uint32_t *off = tile_off + (size_t)t * (nb + 1);
+    if (tid < nb) {
+        off[tid] = start;
+        cur[tid] = start;
+        for (uint32_t q = c; q < pc; ++q) stage[start + q] = kSentinel;
+    }
+    if (tid == 0) off[nb] = total;
+    __syncthreads();
+
+#pragma unroll
+    for (int j = 0; j < kSplitPer / 4; ++j) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int32_t x = v[4 * j + q];
+            if (x >= 0) {
+                const uint32_t o = j * (4 * kSplitThreads) + 4 * tid + q;
+                const uint32_t slot = atomicAdd(&cur[(uint32_t)x >> kVBits], 1u);
+                stage[slot] = (o << kVBits) | ((uint32_t)x & (kBucketW - 1));
+            }
+        }
+    }
+    __syncthreads();
+    v4u *out = (v4u *)(recs + (size_t)t * region);
+    const v4u *st = (const v4u *)stage;
+    for (uint32_t i = tid; i < total / 4; i += kSplitThreads) __builtin_nontemporal_store(st[i], &out[i]);
+}
+
+// out[c][r] = in[r][c] for an rows x cols matrix of uint32.
+__global__ __launch_bounds__(256) void k_transpose(const uint32_t *__restrict__ in, uint32_t rows, uint32_t cols,
+                                                   uint32_t *__restrict__ out) {
+    __shared__ uint32_t tile[32][33];
+    const uint32_t c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+    const uint32_t tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    for (uint32_t y = ty; y < 32; y += 8) {
+        const uint32_t r = r0 + y, c = c0 + tx;
+        if (r < rows && c < cols) tile[y][tx] = in[(size_t)r * cols + c];
+    }
+    __syncthreads();
+    for (uint32_t y = ty; y < 32; y += 8) {
+        const uint32_t c = c0 + y, r = r0 + tx;
+        if (r < rows && c < cols) out[(size_t)c * rows + r] = tile[tx][y];
+    }
+}
+
+// Workgroup (bucket b, slice s) folds the records of tiles [s*tps, (s+1)*tps)
+// into an LDS copy of r for vertices [b*W, (b+1)*W).  Element k of half h has
+// position hbase[h] + stride * k.
+__global__ __launch_bounds__(kMinThreads) void k_bucket_min(const uint32_t *__restrict__ recs,
+                                                            const uint32_t *__restrict__ off_t, uint32_t nt,
+                                                            uint32_t tiles_half, uint32_t region, uint32_t nb,
+                                                            uint32_t tps, uint32_t batch, uint32_t n,
+                                                            uint32_t hbase1, uint32_t stride,
+                                                            uint32_t *__restrict__ out) {
+    __shared__ uint32_t lr[kBucketW];
+    const uint32_t b = blockIdx.x % nb;
+    const uint32_t s = blockIdx.x / nb;
+    const uint32_t t0 = s * tps;
+    const uint32_t t1 = min(nt, t0 + tps);
+    for (uint32_t i = threadIdx.x; i < kBucketW; i += kMinThreads) lr[i] = kInf;
+    __syncthreads();
+
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wave = threadIdx.x / kWave;
+    constexpr uint32_t NWAVE = kMinThreads / kWave;
+    const uint32_t *beg = off_t + (size_t)b * nt;
+    const uint32_t *end = off_t + (size_t)(b + 1) * nt;
+    // A wave takes `batch` (<= 64) tiles at a time: one coalesced load of
+    // their segment bounds, then groups of kMinGroup segments with the next
+    // group's loads issued before the current group is folded in.
+    for (uint32_t tb = t0 + wave * batch; tb < t1; tb += NWAVE * batch) {
+        const uint32_t cnt = min(batch, t1 - tb);
+        const uint32_t my = tb + lane;
+        const uint32_t sb = lane < cnt ? beg[my] : 0u;
+        const uint32_t se = lane < cnt ? end[my] : 0u;
+        uint2 cur[kMinGroup], nxt[kMinGroup];
+        auto load_group = [&](uint32_t g0, uint2 (&dst)[kMinGroup]) {
+#pragma unroll
+            for (int g = 0; g < kMinGroup; ++g) {
+                const uint32_t gi = g0 + g;
+                const uint32_t b0 = __shfl(sb, gi & (kWave - 1), kWave);
+                const uint32_t e0 = __shfl(se, gi & (kWave - 1), kWave);
+                const uint32_t k = b0 + 2 * lane;
+                dst[g] = (gi < cnt && k < e0) ? *(const uint2 *)(recs + (size_t)(tb + gi) * region + k)
+                                              : make_uint2(kSentinel, kSentinel);
+            }
+        };
+        load_group(0, cur);
+        for (uint32_t g0 = 0; g0 < cnt; g0 += kMinGroup) {
+            if (g0 + kMinGroup < cnt) load_group(g0 + kMinGroup, nxt);
+#pragma unroll
+            for (int g = 0; g < kMinGroup; ++g) {
+                const uint32_t gi = g0 + g;
+                const uint32_t tile = tb + gi;
+                const bool h = tile >= tiles_half;
+                const uint32_t pb = (h ? hbase1 : 0u) + stride * ((tile - (h ? tiles_half : 0u)) * kTileT);
+                uint2 x = cur[g];
+                if (x.x != kSentinel) atomicMin(&lr[x.x & (kBucketW - 1)], pb + stride * (x.x >> kVBits));
+                if (x.y != kSentinel) atomicMin(&lr[x.y & (kBucketW - 1)], pb + stride * (x.y >> kVBits));
+                // segments longer than 128 records (rare): finish them here
+                const uint32_t e0 = __shfl(se, gi & (kWave - 1), kWave);
+                uint32_t k = __shfl(sb, gi & (kWave - 1), kWave) + 2 * lane + 2 * kWave;
+                while (gi < cnt && k < e0) {
+                    x = *(const uint2 *)(recs + (size_t)tile * region + k);
+                    if (x.x != kSentinel) atomicMin(&lr[x.x & (kBucketW - 1)], pb + stride * (x.x >> kVBits));
+                    if (x.y != kSentinel) atomicMin(&lr[x.y & (kBucketW - 1)], pb + stride * (x.y >> kVBits));
+                    k += 2 * kWave;
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < kMinGroup; ++g) cur[g] = nxt[g];
+        }
+    }
+    __syncthreads();
+    uint32_t *o = out + (size_t)s * n + (size_t)b * kBucketW;
+    const uint32_t cnt = min(kBucketW, n - b * kBucketW);
+    for (uint32_t i = threadIdx.x; i < cnt; i += kMinThreads) o[i] = lr[i];
+}
+
+// mark with the merge of slice minima: r[v] = min over slices, then set the
+// bitmap bit of key(v).
+__global__ __launch_bounds__(kBlock) void k_mark_merge(uint32_t *__restrict__ rpart, uint32_t slices, uint32_t n,
+                                                       uint32_t tail, uint2 *__restrict__ W) {
+    const uint32_t stride = gridDim.x * kBlock;
+    for (uint32_t v = blockIdx.x * kBlock + threadIdx.x; v < n; v += stride) {
+        uint32_t p = rpart[v];
+        for (uint32_t s = 1; s < slices; ++s) p = min(p, rpart[(size_t)s * n + v]);
+        if (slices > 1) rpart[v] = p;
+        if (p == kInf) p = tail + v;
+        atomicOr(&W[p >> 5].x, 1u << (p & 31));
+    }
+}
+
 inline bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
+// Host-side plan: which scatter path runs and the bucketed path's shape.
+struct ReorderPlan {
+    bool bucketed;
+    uint32_t nb, tiles_half, nt, region, slices, tps;
+};
+
+ReorderPlan reorder_plan(int64_t n, int64_t m) {
+    ReorderPlan P{};
+    P.nb = ceil_div((uint64_t)n, kBucketW);
+    P.tiles_half = ceil_div((uint64_t)m, kTileT);
+    P.nt = 2 * P.tiles_half;
+    P.bucketed = m > 0 && n > 0 && P.nb <= kMaxBuckets;
+    P.slices = 1;
+    if (P.bucketed) {
+        // about 256 workgroups for the bucket pass (one per CU)
+        uint32_t s = ceil_div(256, P.nb);
+        P.slices = s < P.nt ? s : P.nt;
+        if (P.slices < 1) P.slices = 1;
+        P.region = split_region(P.nb);
+    }
+    P.tps = P.nt ? ceil_div(P.nt, P.slices) : 0;
+    return P;
+}
+
 struct ReorderLayout {
-    uint32_t *r;
+    uint32_t *r;  // r = slice 0 of the partial minima
     uint2 *W;
     uint32_t *partial;
+    uint32_t *recs, *tile_off, *off_t;
     size_t bytes;
     uint32_t nw;
 };
 
-ReorderLayout reorder_layout(void *ws, int64_t n, int64_t m) {
+ReorderLayout reorder_layout(void *ws, int64_t n, int64_t m, const ReorderPlan &P) {
     ReorderLayout L;
     const uint64_t positions = 2 * (uint64_t)m + (uint64_t)n;
     L.nw = ceil_div(positions, 32);
     Carver c(ws);
-    L.r = c.take<uint32_t>((size_t)n);
     L.W = c.take<uint2>(L.nw);
     L.partial = c.take<uint32_t>(scan_partials(L.nw));
+    L.r = c.take<uint32_t>((size_t)n * P.slices);
+    L.recs = c.take<uint32_t>(P.bucketed ? (size_t)P.nt * P.region : 0);
+    L.tile_off = c.take<uint32_t>(P.bucketed ? (size_t)P.nt * (P.nb + 1) : 0);
+    L.off_t = c.take<uint32_t>(P.bucketed ? (size_t)P.nt * (P.nb + 1) : 0);
     L.bytes = c.bytes();
     return L;
 }
@@ -246,7 +493,7 @@ using namespace boba;
 
 extern "C" size_t boba_reorder_workspace(int64_t n, int64_t m) {
     if (n < 0 || m < 0) return 0;
-    return reorder_layout(nullptr, n, m).bytes;
+    return reorder_layout(nullptr, n, m, reorder_plan(n, m)).bytes;
 }
 
 extern "C" boba_status boba_reorder(const int32_t *src, const int32_t *dst, int64_t m, int64_t n, int32_t *perm,
@@ -267,39 +514,58 @@ extern "C" boba_status boba_reorder(const int32_t *src, const int32_t *dst, int6
 
     const bool inter = flags & BOBA_FLAG_INTERLEAVED;
     const uint32_t un = (uint32_t)n, um = (uint32_t)m;
-    ReorderLayout L = reorder_layout(ws, n, m);
-
-    BOBA_LAUNCH("reorder_init", k_reorder_init, dim3(grid_for(un > L.nw ? un : L.nw, kBlock * 4)), dim3(kBlock),
-                stream, L.r, un, L.W, L.nw);
-
-    uint32_t k0 = 0;
-    if (m > 0 && aligned16(src) && aligned16(dst)) {
-        const uint32_t m4 = um / 4;
-        if (m4 > 0) {
-            dim3 grid(ceil_div(2ull * m4, kScatterTile));
-            if (inter)
-                BOBA_LAUNCH("scatter_min", k_scatter_min_vec<true>, grid, dim3(kBlock), stream, (const v4i *)src,
-                            (const v4i *)dst, m4, um, un, L.r, flag);
-            else
-                BOBA_LAUNCH("scatter_min", k_scatter_min_vec<false>, grid, dim3(kBlock), stream, (const v4i *)src,
-                            (const v4i *)dst, m4, um, un, L.r, flag);
-        }
-        k0 = 4 * m4;
-    }
-    if (k0 < um) {
-        dim3 grid(grid_for(2ull * (um - k0), kBlock));
-        if (inter)
-            BOBA_LAUNCH("scatter_min_scalar", k_scatter_min_scalar<true>, grid, dim3(kBlock), stream, src, dst, k0, um,
-                        un, L.r, flag);
-        else
-            BOBA_LAUNCH("scatter_min_scalar", k_scatter_min_scalar<false>, grid, dim3(kBlock), stream, src, dst, k0,
-                        um, un, L.r, flag);
-    }
-
+    const ReorderPlan P = reorder_plan(n, m);
+    const ReorderLayout L = reorder_layout(ws, n, m, P);
+    const bool bucketed = P.bucketed && aligned16(src) && aligned16(dst);
     const uint32_t tail = 2 * um;
-    BOBA_LAUNCH("mark", k_mark, dim3(grid_for(un, kBlock * 4)), dim3(kBlock), stream, (const uint32_t *)L.r, un, tail,
-                L.W);
-    if (boba_status e = device_scan<OpSum, false>("bitmap_scan", LoadPopc{L.W}, StorePrefix{L.W}, L.nw, L.partial, stream))
+
+    if (bucketed) {
+        BOBA_LAUNCH("reorder_init", k_reorder_init, dim3(grid_for(L.nw, kBlock * 4)), dim3(kBlock), stream, L.r, 0u,
+                    L.W, L.nw);
+        BOBA_LAUNCH("bucket_split", k_bucket_split, dim3(P.nt), dim3(kSplitThreads), stream, src, dst, um,
+                    P.tiles_half, un, P.nb, P.region, L.recs, L.tile_off, flag);
+        BOBA_LAUNCH("bucket_transpose", k_transpose, dim3(ceil_div(P.nb + 1, 32), ceil_div(P.nt, 32)), dim3(256),
+                    stream, (const uint32_t *)L.tile_off, P.nt, P.nb + 1, L.off_t);
+        // tiles per wave step: spread a slice's tiles over all 16 waves
+        uint32_t batch = ceil_div(P.tps, kMinThreads / kWave);
+        batch = (batch + kMinGroup - 1) / kMinGroup * kMinGroup;
+        batch = batch < (uint32_t)kMinGroup ? kMinGroup : (batch > (uint32_t)kWave ? kWave : batch);
+        BOBA_LAUNCH("bucket_min", k_bucket_min, dim3(P.nb * P.slices), dim3(kMinThreads), stream,
+                    (const uint32_t *)L.recs, (const uint32_t *)L.off_t, P.nt, P.tiles_half, P.region, P.nb, P.tps,
+                    batch, un, inter ? 1u : um, inter ? 2u : 1u, L.r);
+        BOBA_LAUNCH("mark", k_mark_merge, dim3(grid_for(un, kBlock * 4)), dim3(kBlock), stream, L.r, P.slices, un,
+                    tail, L.W);
+    } else {
+        BOBA_LAUNCH("reorder_init", k_reorder_init, dim3(grid_for(un > L.nw ? un : L.nw, kBlock * 4)),
+                    dim3(kBlock), stream, L.r, un, L.W, L.nw);
+        uint32_t k0 = 0;
+        if (m > 0 && aligned16(src) && aligned16(dst)) {
+            const uint32_t m4 = um / 4;
+            if (m4 > 0) {
+                dim3 grid(ceil_div(2ull * m4, kScatterTile));
+                if (inter)
+                    BOBA_LAUNCH("scatter_min", k_scatter_min_vec<true>, grid, dim3(kBlock), stream,
+                                (const v4i *)src, (const v4i *)dst, m4, um, un, L.r, flag);
+                else
+                    BOBA_LAUNCH("scatter_min", k_scatter_min_vec<false>, grid, dim3(kBlock), stream,
+                                (const v4i *)src, (const v4i *)dst, m4, um, un, L.r, flag);
+            }
+            k0 = 4 * m4;
+        }
+        if (k0 < um) {
+            dim3 grid(grid_for(2ull * (um - k0), kBlock));
+            if (inter)
+                BOBA_LAUNCH("scatter_min_scalar", k_scatter_min_scalar<true>, grid, dim3(kBlock), stream, src, dst,
+                            k0, um, un, L.r, flag);
+            else
+                BOBA_LAUNCH("scatter_min_scalar", k_scatter_min_scalar<false>, grid, dim3(kBlock), stream, src, dst,
+                            k0, um, un, L.r, flag);
+        }
+        BOBA_LAUNCH("mark", k_mark, dim3(grid_for(un, kBlock * 4)), dim3(kBlock), stream, (const uint32_t *)L.r, un,
+                    tail, L.W);
+    }
+    if (boba_status e = device_scan<OpSum, false>("bitmap_scan", LoadPopc{L.W}, StorePrefix{L.W}, L.nw, L.partial,
+                                                  stream))
         return e;
     BOBA_LAUNCH("rank", k_rank, dim3(grid_for(un, kBlock * 4)), dim3(kBlock), stream, (const uint32_t *)L.r, un, tail,
                 (const uint2 *)L.W, perm, order);

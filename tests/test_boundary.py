@@ -105,10 +105,16 @@ def test_relabel_csr_spmv_argument_errors(lib):
     assert lib.coo_to_csr(FAKE, FAKE, None, 3, 5, FAKE, FAKE, None, FAKE, need - 1, None) == boba.BOBA_ERR_WORKSPACE
     assert lib.coo_to_csr(FAKE, FAKE, None, 3, 0, FAKE, FAKE, None, FAKE, need, None) == boba.BOBA_ERR_ARG
     assert lib.coo_to_csr(FAKE, FAKE, None, -3, 5, FAKE, FAKE, None, FAKE, need, None) == boba.BOBA_ERR_ARG
-    assert lib.spmv_csr(FAKE, FAKE, None, -1, 5, FAKE, FAKE, None) == boba.BOBA_ERR_ARG
-    assert lib.spmv_csr(None, FAKE, None, 4, 5, FAKE, FAKE, None) == boba.BOBA_ERR_ARG
-    assert lib.spmv_csr(FAKE, FAKE, None, 1 << 31, 5, FAKE, FAKE, None) == boba.BOBA_ERR_OVERFLOW
-    assert lib.spmv_csr(None, None, None, 0, 0, None, None, None) == boba.BOBA_OK
+    sw = lib.spmv_csr_workspace(4, 3)
+    assert lib.spmv_csr(FAKE, FAKE, None, -1, 5, 3, FAKE, FAKE, FAKE, sw, None) == boba.BOBA_ERR_ARG
+    assert lib.spmv_csr(FAKE, FAKE, None, 4, 5, -3, FAKE, FAKE, FAKE, sw, None) == boba.BOBA_ERR_ARG
+    assert lib.spmv_csr(None, FAKE, None, 4, 5, 3, FAKE, FAKE, FAKE, sw, None) == boba.BOBA_ERR_ARG
+    assert lib.spmv_csr(FAKE, None, None, 4, 5, 3, FAKE, FAKE, FAKE, sw, None) == boba.BOBA_ERR_ARG
+    assert lib.spmv_csr(FAKE, FAKE, None, 4, 5, 3, FAKE, None, FAKE, sw, None) == boba.BOBA_ERR_ARG
+    assert lib.spmv_csr(FAKE, FAKE, None, 4, 5, 3, FAKE, FAKE, None, sw, None) == boba.BOBA_ERR_WORKSPACE
+    assert lib.spmv_csr(FAKE, FAKE, None, 4, 5, 3, FAKE, FAKE, FAKE, sw - 1, None) == boba.BOBA_ERR_WORKSPACE
+    assert lib.spmv_csr(FAKE, FAKE, None, 1 << 31, 5, 3, FAKE, FAKE, FAKE, sw, None) == boba.BOBA_ERR_OVERFLOW
+    assert lib.spmv_csr(None, None, None, 0, 0, 0, None, None, None, 0, None) == boba.BOBA_OK
     assert lib.boba_check_device_error(None, None) == boba.BOBA_ERR_ARG
 
 

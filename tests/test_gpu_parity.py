@@ -193,3 +193,42 @@ def test_out_of_range_ids_set_the_device_flag():
     rp = dev(np.array([0, 2, 4], np.int32))
     boba.spmv_csr(rp, d, None, torch.ones(4, device="cuda"))
     assert boba.boba_check_device_error() == boba.BOBA_ERR_RANGE
+
+
+def test_more_than_2_25_vertices_uses_the_direct_path():
+    # 2^25 + 7 vertices exceed the bucketed path's LDS bucket budget
+    n = (1 << 25) + 7
+    g = graphgen.Graph("bign", n, *graphgen.uniform_edges(n, 300001, 84))
+    perm, order = boba.boba_reorder(dev(g.src), dev(g.dst), n)
+    p_ref, o_ref = oracle.boba(g.src, g.dst, n)
+    assert np.array_equal(host(perm), p_ref) and np.array_equal(host(order), o_ref)
+
+
+@pytest.mark.parametrize("n", [32767, 32768, 32769, 65536 * 3 + 1])
+def test_bucket_boundaries(n):
+    g = graphgen.small_workload("uniform", n, 3 * n + 1, 85 + n)
+    full_path_check(g, boba)
+    full_path_check(g, boba, interleaved=True, check_spmv=False)
+
+
+@pytest.mark.parametrize("lengths", [
+    [0, 4096, 1, 0, 4095, 4097, 65, 64, 0, 100000, 3, 0, 0],
+    [8192, 0, 0, 1, 4096 * 3 - 1, 2, 70000, 5],
+    [1] * 9000 + [5000] + [0] * 300 + [64, 65, 63] * 50,
+])
+def test_spmv_rows_across_chunk_boundaries(lengths):
+    rng = np.random.default_rng(len(lengths))
+    n_cols = 7777
+    rowptr = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int32)
+    nnz = int(rowptr[-1])
+    col = rng.integers(0, n_cols, nnz).astype(np.int32)
+    val = rng.uniform(-1, 1, nnz).astype(np.float32)
+    x = rng.uniform(-1, 1, n_cols).astype(np.float32)
+    y = host(boba.spmv_csr(dev(rowptr), dev(col), dev(val), dev(x)))
+    y_ref = oracle.spmv64(rowptr, col, val, x)
+    assert rel_l2(y, y_ref) <= SPMV_TOL
+    # rows of length 0 or 1 are exact
+    short = np.diff(rowptr) <= 1
+    assert np.array_equal(y[short], y_ref[short].astype(np.float32))
+    # each row individually close
+    assert np.all(np.abs(y - y_ref) <= 1e-4 * (1 + np.abs(y_ref)) + 1e-5 * np.sqrt(np.diff(rowptr)))
