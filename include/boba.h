@@ -122,6 +122,46 @@ BOBA_API boba_status spmv_csr(const int32_t *rowptr, const int32_t *col, const f
                               int64_t n_rows, int64_t n_cols, int64_t nnz, const float *x, float *y,
                               void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* ------------------------------------------------------------- batched ---
+ * Many graphs reordered (and optionally relabelled) at once by one persistent
+ * kernel replayed from a hipGraph.  Per graph the result is exactly that of
+ * boba_reorder (+ boba_relabel) on the graph alone; this batching is not in the
+ * paper, whose method is per graph (Sec. 4.4).
+ *   G             number of graphs.
+ *   h_edge_off    host int64[G+1], h_edge_off[0] = 0: graph g owns edges
+ *                 [h_edge_off[g], h_edge_off[g+1]) of src/dst (and src_out/dst_out).
+ *   h_vert_off    host int64[G+1], h_vert_off[0] = 0: graph g has
+ *                 n_g = h_vert_off[g+1] - h_vert_off[g] vertices, local IDs
+ *                 [0, n_g); its perm/order live at [h_vert_off[g], ...).
+ *   src, dst      int32[total m] concatenated local edge lists.
+ *   perm          int32[total n] output (local new IDs);  order may be NULL.
+ *   src_out, dst_out  int32[total m] relabelled edges, or both NULL (reorder only).
+ *   ws            at least boba_batch_workspace(...) bytes, 256-byte aligned; the
+ *                 plan keeps pointers into it, so it must outlive the plan.
+ *   tuning        NULL for defaults, else see boba_tuning (0 fields = default).
+ * plan_create uploads the plan's tables on `stream` (and waits for them) and
+ * captures the hipGraph; the inputs need not be ready yet.  plan_launch
+ * replays it on `stream`.  A plan is bound to the pointers given at creation;
+ * it is not thread-safe; destroy it before freeing the workspace.  Totals must
+ * be < 2^31; each graph must satisfy boba_reorder's limits. */
+typedef struct boba_tuning {
+    int32_t small_max_n;  /* graphs with n_g <= this run whole in one workgroup (max 32768) */
+    int32_t scatter_tile; /* positions per scatter item of a large graph (default 262144) */
+    int32_t vertex_tile;  /* vertices per mark / rank item (default 65536) */
+    int32_t relabel_tile; /* edges per relabel item (default 262144) */
+} boba_tuning;
+typedef struct boba_batch_plan boba_batch_plan;
+BOBA_API size_t boba_batch_workspace(int32_t G, const int64_t *h_edge_off, const int64_t *h_vert_off,
+                                     const boba_tuning *tuning);
+BOBA_API boba_status boba_batch_plan_create(int32_t G, const int64_t *h_edge_off, const int64_t *h_vert_off,
+                                            const int32_t *src, const int32_t *dst, int32_t *perm, int32_t *order,
+                                            int32_t *src_out, int32_t *dst_out, void *ws, size_t ws_bytes,
+                                            const boba_tuning *tuning, hipStream_t stream, boba_batch_plan **plan);
+BOBA_API boba_status boba_batch_plan_launch(boba_batch_plan *plan, hipStream_t stream);
+/* info4 (host): items, whole-graph items, r words, bitmap words. */
+BOBA_API boba_status boba_batch_plan_info(const boba_batch_plan *plan, int64_t *info4);
+BOBA_API boba_status boba_batch_plan_destroy(boba_batch_plan *plan);
+
 /* -------------------------------------------------------------- timing ---
  * Per-kernel timing with HIP events, for benchmarks (off by default).  While
  * enabled, every kernel the library launches outside stream capture is

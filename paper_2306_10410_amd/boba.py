@@ -32,6 +32,11 @@ PROTOTYPES = {
     "coo_to_csr": (_I32, [_P, _P, _P, _I64, _I64, _P, _P, _P, _P, _SZ, _P]),
     "spmv_csr_workspace": (_SZ, [_I64, _I64]),
     "spmv_csr": (_I32, [_P, _P, _P, _I64, _I64, _I64, _P, _P, _P, _SZ, _P]),
+    "boba_batch_workspace": (_SZ, [_I32, _P, _P, _P]),
+    "boba_batch_plan_create": (_I32, [_I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P, _P, _P]),
+    "boba_batch_plan_launch": (_I32, [_P, _P]),
+    "boba_batch_plan_info": (_I32, [_P, _P]),
+    "boba_batch_plan_destroy": (_I32, [_P]),
     "boba_timing_enable": (_I32, [_I32]),
     "boba_timing_collect": (_I32, [_P, _SZ, _P, _P, _I32]),
 }
@@ -176,3 +181,69 @@ def boba_timing_collect(max_entries: int = 64):
     k = load().boba_timing_collect(buf, len(buf), ms, cnt, max_entries)
     names = buf.raw.split(b"\0")[:k]
     return {names[i].decode(): (ms[i], cnt[i]) for i in range(k)}
+
+
+class boba_tuning(ctypes.Structure):
+    """Mirror of struct boba_tuning (0 = library default)."""
+    _fields_ = [("small_max_n", ctypes.c_int32), ("scatter_tile", ctypes.c_int32),
+                ("vertex_tile", ctypes.c_int32), ("relabel_tile", ctypes.c_int32)]
+
+
+def _host_i64(a):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def boba_batch_workspace(edge_off, vert_off, tuning=None) -> int:
+    eo, peo = _host_i64(edge_off)
+    vo, pvo = _host_i64(vert_off)
+    return int(load().boba_batch_workspace(len(eo) - 1, peo, pvo, ctypes.byref(tuning) if tuning else None))
+
+
+class BatchPlan:
+    """A captured batched reorder (+relabel).  Keeps the tensors it was built
+    on alive; launch() replays it on the current (or given) stream."""
+
+    def __init__(self, edge_off, vert_off, src, dst, *, relabel=True, with_order=True, tuning=None,
+                 stream=None):
+        _dev_i32(src, "src")
+        _dev_i32(dst, "dst")
+        eo, peo = _host_i64(edge_off)
+        vo, pvo = _host_i64(vert_off)
+        G = len(eo) - 1
+        dev = src.device
+        self.src, self.dst = src, dst
+        self.perm = torch.empty(int(vo[-1]), dtype=torch.int32, device=dev)
+        self.order = torch.empty(int(vo[-1]), dtype=torch.int32, device=dev) if with_order else None
+        self.src_out = torch.empty_like(src) if relabel else None
+        self.dst_out = torch.empty_like(dst) if relabel else None
+        tp = ctypes.byref(tuning) if tuning else None
+        need = int(load().boba_batch_workspace(G, peo, pvo, tp))
+        if need == 0 and G > 0:
+            raise BobaError(BOBA_ERR_ARG, "invalid batch description")
+        self.ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+        self._plan = ctypes.c_void_p()
+        _check(load().boba_batch_plan_create(G, peo, pvo, _ptr(src), _ptr(dst), _ptr(self.perm), _ptr(self.order),
+                                             _ptr(self.src_out), _ptr(self.dst_out), _ptr(self.ws), self.ws.numel(),
+                                             tp, _stream(stream), ctypes.byref(self._plan)))
+
+    def launch(self, stream=None):
+        _check(load().boba_batch_plan_launch(self._plan, _stream(stream)))
+        return self
+
+    def info(self):
+        out = (ctypes.c_int64 * 4)()
+        _check(load().boba_batch_plan_info(self._plan, out))
+        return {"items": out[0], "whole_graph_items": out[1], "r_words": out[2], "bitmap_words": out[3]}
+
+    def destroy(self):
+        if self._plan:
+            _check(load().boba_batch_plan_destroy(self._plan))
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -303,3 +303,28 @@ def make_batch_graph(spec: BatchSpec):
         src, dst = rgg(n, math.sqrt(spec.edge_factor / (math.pi * n)), spec.seed)
     sigma = random_labels(n, spec.seed + 1)
     return apply_labels(src, dst, sigma)
+
+
+def _batch_job(spec):
+    return make_batch_graph(spec)
+
+
+def make_batch(specs, workers: int = 0):
+    """Generate the graphs of `specs` and concatenate them.  Returns
+    (edge_off[G+1], vert_off[G+1], src, dst) with local vertex IDs per graph.
+    workers > 1 uses forked worker processes: call it before the parent
+    process touches the GPU."""
+    if workers > 1:
+        import multiprocessing as mp
+        from concurrent.futures import ProcessPoolExecutor
+        with ProcessPoolExecutor(workers, mp_context=mp.get_context("fork")) as ex:
+            parts = list(ex.map(_batch_job, specs, chunksize=4))
+    else:
+        parts = [make_batch_graph(s) for s in specs]
+    m = np.array([p[0].size for p in parts], np.int64)
+    n = np.array([s.n for s in specs], np.int64)
+    edge_off = np.concatenate([[0], np.cumsum(m)]).astype(np.int64)
+    vert_off = np.concatenate([[0], np.cumsum(n)]).astype(np.int64)
+    src = np.concatenate([p[0] for p in parts]) if parts else np.zeros(0, np.int32)
+    dst = np.concatenate([p[1] for p in parts]) if parts else np.zeros(0, np.int32)
+    return edge_off, vert_off, src, dst

@@ -123,3 +123,30 @@ def test_binding_refuses_host_tensors():
     x = torch.zeros(4, dtype=torch.int32)
     with pytest.raises(TypeError):
         boba.boba_reorder(x, x, 4)
+
+
+def test_batch_argument_errors(lib):
+    import numpy as np
+    eo = np.array([0, 5, 9], np.int64)
+    vo = np.array([0, 3, 7], np.int64)
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    assert lib.boba_batch_workspace(2, p(eo), p(vo), None) > 0
+    bad = np.array([0, 5, 4], np.int64)  # decreasing
+    assert lib.boba_batch_workspace(2, p(bad), p(vo), None) == 0
+    plan = ctypes.c_void_p()
+    need = lib.boba_batch_workspace(2, p(eo), p(vo), None)
+    assert lib.boba_batch_plan_create(2, p(eo), p(vo), FAKE, FAKE, FAKE, None, None, None, FAKE, need, None, None,
+                                      None) == boba.BOBA_ERR_ARG
+    assert lib.boba_batch_plan_create(2, p(eo), p(vo), FAKE, FAKE, FAKE, None, FAKE, None, FAKE, need, None, None,
+                                      ctypes.byref(plan)) == boba.BOBA_ERR_ARG
+    assert lib.boba_batch_plan_create(2, p(eo), p(vo), None, FAKE, FAKE, None, None, None, FAKE, need, None, None,
+                                      ctypes.byref(plan)) == boba.BOBA_ERR_ARG
+    assert lib.boba_batch_plan_create(2, p(eo), p(vo), FAKE, FAKE, None, None, None, None, FAKE, need, None, None,
+                                      ctypes.byref(plan)) == boba.BOBA_ERR_ARG
+    assert lib.boba_batch_plan_create(2, p(eo), p(vo), FAKE, FAKE, FAKE, None, None, None, FAKE, need - 1, None, None,
+                                      ctypes.byref(plan)) == boba.BOBA_ERR_WORKSPACE
+    assert lib.boba_batch_plan_create(2, p(bad), p(vo), FAKE, FAKE, FAKE, None, None, None, FAKE, need, None, None,
+                                      ctypes.byref(plan)) == boba.BOBA_ERR_ARG
+    assert not plan.value
+    assert lib.boba_batch_plan_launch(None, None) == boba.BOBA_ERR_ARG
+    assert lib.boba_batch_plan_destroy(None) == boba.BOBA_OK

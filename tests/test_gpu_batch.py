@@ -1,0 +1,96 @@
+"""Batched persistent reorder (+relabel) against the oracle, graph by graph,
+over replays of the captured hipGraph and over tuning choices."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2306_10410_amd import boba, graphgen
+from gpu_util import dev, host, requires_gpu
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+
+def mixed_batch(seed=5):
+    specs = graphgen.batch_specs(24, seed=seed, log2_lo=4.0, log2_hi=17.2)
+    graphs = [graphgen.make_batch_graph(s) for s in specs]
+    ns = [s.n for s in specs]
+    # degenerate members: no edges, one vertex with self-loops, isolated tail
+    graphs += [(np.zeros(0, np.int32), np.zeros(0, np.int32)), (np.zeros(5, np.int32), np.zeros(5, np.int32)),
+               (np.array([3, 3], np.int32), np.array([1, 0], np.int32))]
+    ns += [17, 1, 40000]
+    m = np.array([g[0].size for g in graphs], np.int64)
+    eo = np.concatenate([[0], np.cumsum(m)]).astype(np.int64)
+    vo = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+    return eo, vo, np.concatenate([g[0] for g in graphs]), np.concatenate([g[1] for g in graphs])
+
+
+def check_against_oracle(eo, vo, src, dst, perm, order, so, do):
+    for g in range(len(eo) - 1):
+        a, b = eo[g], eo[g + 1]
+        n = int(vo[g + 1] - vo[g])
+        p_ref, o_ref = oracle.boba(src[a:b], dst[a:b], n)
+        assert np.array_equal(perm[vo[g]:vo[g + 1]], p_ref), f"perm of graph {g} (n={n}, m={b - a})"
+        if order is not None:
+            assert np.array_equal(order[vo[g]:vo[g + 1]], o_ref), f"order of graph {g}"
+        if so is not None:
+            s_ref, d_ref = oracle.relabel(src[a:b], dst[a:b], p_ref)
+            assert np.array_equal(so[a:b], s_ref) and np.array_equal(do[a:b], d_ref), f"relabel of graph {g}"
+
+
+@pytest.fixture(scope="module")
+def batch():
+    return mixed_batch()
+
+
+def test_batched_equals_per_graph_over_replays(batch):
+    eo, vo, src, dst = batch
+    s, d = dev(src), dev(dst)
+    plan = boba.BatchPlan(eo, vo, s, d)
+    info = plan.info()
+    assert info["whole_graph_items"] > 0 and info["items"] > info["whole_graph_items"]  # both paths used
+    for rep in range(3):
+        plan.launch()
+        torch.cuda.synchronize()
+        check_against_oracle(eo, vo, src, dst, host(plan.perm), host(plan.order), host(plan.src_out),
+                             host(plan.dst_out))
+        # eager work between replays: clobber the outputs
+        plan.perm.fill_(-7)
+        plan.src_out.fill_(-7)
+        plan.order.zero_()
+        torch.cuda.synchronize()
+    assert boba.boba_check_device_error() == boba.BOBA_OK
+    plan.destroy()
+
+
+@pytest.mark.parametrize("tuning", [(1024, 4096, 1024, 8192), (32768, 1 << 20, 1 << 20, 1 << 20), (1, 1000, 777, 5000)])
+def test_tuning_never_changes_results(batch, tuning):
+    eo, vo, src, dst = batch
+    tu = boba.boba_tuning(*tuning)
+    plan = boba.BatchPlan(eo, vo, dev(src), dev(dst), tuning=tu)
+    plan.launch()
+    check_against_oracle(eo, vo, src, dst, host(plan.perm), host(plan.order), host(plan.src_out),
+                         host(plan.dst_out))
+    assert boba.boba_check_device_error() == boba.BOBA_OK
+    plan.destroy()
+
+
+def test_reorder_only_plan(batch):
+    eo, vo, src, dst = batch
+    plan = boba.BatchPlan(eo, vo, dev(src), dev(dst), relabel=False, with_order=False)
+    plan.launch()
+    check_against_oracle(eo, vo, src, dst, host(plan.perm), None, None, None)
+    plan.destroy()
+
+
+def test_batched_matches_single_graph_entry_point(batch):
+    eo, vo, src, dst = batch
+    plan = boba.BatchPlan(eo, vo, dev(src), dev(dst))
+    plan.launch()
+    perm_b = host(plan.perm)
+    for g in [0, 3, 7, len(eo) - 2]:
+        a, b = eo[g], eo[g + 1]
+        n = int(vo[g + 1] - vo[g])
+        p, _ = boba.boba_reorder(dev(src[a:b]), dev(dst[a:b]), n)
+        assert np.array_equal(host(p), perm_b[vo[g]:vo[g + 1]])
+    plan.destroy()
