@@ -125,6 +125,9 @@ def main():
     ap.add_argument("--before-reps", type=int, default=5)
     ap.add_argument("--batch-graphs", type=int, default=512, help="graphs in the batched measurement (0: skip)")
     ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--calibrate", action="store_true",
+                    help="run a plain elementwise kernel over 256 MiB (reads and writes 256 MiB) first, "
+                         "to scale hardware byte counters")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -180,6 +183,14 @@ def main():
     y = torch.empty(n, dtype=torch.float32, device=dev)
     x2 = torch.empty(n, dtype=torch.float32, device=dev)
     ws_s = torch.empty(boba.spmv_csr_workspace(n, m), dtype=torch.uint8, device=dev)
+
+    if args.calibrate:
+        a = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.neg(a, out=b)
+        torch.cuda.synchronize()
+        del a, b
 
     stage_names = ["reorder", "relabel", "coo_to_csr", "spmv"]
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]

@@ -162,6 +162,42 @@ BOBA_API boba_status boba_batch_plan_launch(boba_batch_plan *plan, hipStream_t s
 BOBA_API boba_status boba_batch_plan_info(const boba_batch_plan *plan, int64_t *info4);
 BOBA_API boba_status boba_batch_plan_destroy(boba_batch_plan *plan);
 
+/* ------------------------------------------------------------ selector ---
+ * A learned "will reordering pay off" selector (not in the paper; it targets
+ * the net-speedup question of Sec. 1.1, Problem 2).
+ *
+ * boba_graph_features: 16 FP32 features of an edge list from n, m, 4096
+ * evenly spread samples and 64 windows of min(1024, m) consecutive edges:
+ *   0 log2(1+n)  1 log2(1+m)  2 log2(1 + m/max(n,1))
+ *   3,4  log2(1 + n*C/(K(K-1)/2)), C = equal pairs among the src (dst) samples
+ *   5,6  log2(1 + n*maxcount/K)   7,8  distinct samples / K   (K = 4096)
+ *   9    window mean of sum|src-dst| / (L*n)
+ *   10,11 window mean of #distinct (id >> 5) / L
+ *   12,13 window mean of #(id_e == id_{e-1}) / (L-1)
+ *   14,15 window mean of #(|id_e - id_{e-1}| < 32) / (L-1)
+ * where sample k is edge floor(k*m/K) and window w starts at edge
+ * floor(w*(m-L)/63).  feat16 is a device float[16]; ws at least
+ * boba_graph_features_workspace() bytes, 256-byte aligned.
+ *
+ * MLP 16 -> 64 -> 64 -> 1 with ReLU, FP32, parameters row-major in one device
+ * array of boba_mlp_param_count() = 5313 floats: W1[64][16] b1[64] W2[64][64]
+ * b2[64] W3[1][64] b3[1].  X is float[B][16], y and yhat float[B].
+ * boba_mlp_backward writes grad (float[5313]) of loss = mean((yhat - y)^2) and
+ * loss (float[1]); ws at least boba_mlp_backward_workspace(B) bytes.
+ * boba_mlp_adam updates params, m1, m2 (float[count]) in place with one Adam
+ * step number t >= 1 (bias-corrected).  All reductions have a fixed order. */
+BOBA_API size_t boba_graph_features_workspace(void);
+BOBA_API boba_status boba_graph_features(const int32_t *src, const int32_t *dst, int64_t m, int64_t n,
+                                         float *feat16, void *ws, size_t ws_bytes, hipStream_t stream);
+BOBA_API int32_t boba_mlp_param_count(void);
+BOBA_API boba_status boba_mlp_forward(const float *params, const float *X, int32_t B, float *yhat,
+                                      hipStream_t stream);
+BOBA_API size_t boba_mlp_backward_workspace(int32_t B);
+BOBA_API boba_status boba_mlp_backward(const float *params, const float *X, const float *y, int32_t B,
+                                       float *grad, float *loss, void *ws, size_t ws_bytes, hipStream_t stream);
+BOBA_API boba_status boba_mlp_adam(float *params, float *m1, float *m2, const float *grad, int32_t count,
+                                   int32_t t, float lr, float b1, float b2, float eps, hipStream_t stream);
+
 /* -------------------------------------------------------------- timing ---
  * Per-kernel timing with HIP events, for benchmarks (off by default).  While
  * enabled, every kernel the library launches outside stream capture is

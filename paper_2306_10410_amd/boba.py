@@ -37,6 +37,14 @@ PROTOTYPES = {
     "boba_batch_plan_launch": (_I32, [_P, _P]),
     "boba_batch_plan_info": (_I32, [_P, _P]),
     "boba_batch_plan_destroy": (_I32, [_P]),
+    "boba_graph_features_workspace": (_SZ, []),
+    "boba_graph_features": (_I32, [_P, _P, _I64, _I64, _P, _P, _SZ, _P]),
+    "boba_mlp_param_count": (_I32, []),
+    "boba_mlp_forward": (_I32, [_P, _P, _I32, _P, _P]),
+    "boba_mlp_backward_workspace": (_SZ, [_I32]),
+    "boba_mlp_backward": (_I32, [_P, _P, _P, _I32, _P, _P, _P, _SZ, _P]),
+    "boba_mlp_adam": (_I32, [_P, _P, _P, _P, _I32, _I32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                              ctypes.c_float, _P]),
     "boba_timing_enable": (_I32, [_I32]),
     "boba_timing_collect": (_I32, [_P, _SZ, _P, _P, _I32]),
 }
@@ -247,3 +255,53 @@ class BatchPlan:
             self.destroy()
         except Exception:
             pass
+
+
+def _dev_f32(t, name):
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float32 device tensor")
+    return t
+
+
+def boba_graph_features(src, dst, n: int, *, out=None, ws=None, stream=None):
+    """16 FP32 features (device tensor) of an edge list."""
+    _dev_i32(src, "src")
+    _dev_i32(dst, "dst")
+    out = torch.empty(16, dtype=torch.float32, device=src.device) if out is None else out
+    ws = _workspace(int(load().boba_graph_features_workspace()), src.device, ws)
+    _check(load().boba_graph_features(_ptr(src), _ptr(dst), src.numel(), n, _ptr(out), _ptr(ws), ws.numel(),
+                                      _stream(stream)))
+    return out
+
+
+def boba_mlp_param_count() -> int:
+    return int(load().boba_mlp_param_count())
+
+
+def boba_mlp_forward(params, X, *, out=None, stream=None):
+    _dev_f32(params, "params")
+    _dev_f32(X, "X")
+    B = X.shape[0]
+    out = torch.empty(B, dtype=torch.float32, device=X.device) if out is None else out
+    _check(load().boba_mlp_forward(_ptr(params), _ptr(X), B, _ptr(out), _stream(stream)))
+    return out
+
+
+def boba_mlp_backward(params, X, y, *, grad=None, loss=None, ws=None, stream=None):
+    _dev_f32(params, "params")
+    _dev_f32(X, "X")
+    _dev_f32(y, "y")
+    B = X.shape[0]
+    grad = torch.empty_like(params) if grad is None else grad
+    loss = torch.empty(1, dtype=torch.float32, device=X.device) if loss is None else loss
+    ws = _workspace(int(load().boba_mlp_backward_workspace(B)), X.device, ws)
+    _check(load().boba_mlp_backward(_ptr(params), _ptr(X), _ptr(y), B, _ptr(grad), _ptr(loss), _ptr(ws), ws.numel(),
+                                    _stream(stream)))
+    return grad, loss
+
+
+def boba_mlp_adam(params, m1, m2, grad, t: int, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+    for a, nm in ((params, "params"), (m1, "m1"), (m2, "m2"), (grad, "grad")):
+        _dev_f32(a, nm)
+    _check(load().boba_mlp_adam(_ptr(params), _ptr(m1), _ptr(m2), _ptr(grad), params.numel(), t, lr, b1, b2, eps,
+                                _stream(stream)))

@@ -1,0 +1,326 @@
+"""Learned reorder selector: will BOBA pay for itself on this graph?
+
+Not part of the paper's method: it answers the net-speedup question of the
+paper's Problem 2 (Sec. 1.1) per graph instead of reordering every graph.
+
+Serving path (all on the GPU, through the C ABI):
+    boba_graph_features (16 FP32 features) -> boba_mlp_forward -> one float
+    prediction of log2(T_never / T_always) -> reorder iff it is > 0.
+The feature standardisation used in training is folded into the first layer,
+so the deployed network takes raw features.  Without a usable model, or when
+a feature or the prediction is not finite, the policy falls back to always
+reordering (the method itself).
+
+Labels are measured by the method itself on the GPU:
+    T_never  = t(coo_to_csr on input labels) + spmv_iters * t(spmv on it)
+    T_always = t(boba_reorder) + t(boba_relabel) + t(coo_to_csr on BOBA labels)
+               + spmv_iters * t(spmv on it)
+each the median of `reps` HIP-event timings.  Training uses the library's own
+backward and Adam kernels.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import graphgen
+
+N_FEAT = 16
+SPMV_ITERS = 20
+
+
+# --------------------------------------------------------------------- timing
+def _events(torch, k):
+    return [torch.cuda.Event(enable_timing=True) for _ in range(k)]
+
+
+def measure_paths(src, dst, val, x, n, *, reps=5, spmv_iters=SPMV_ITERS, ws=None):
+    """Times both paths on device tensors.  Returns a dict of median ms."""
+    import torch
+
+    from . import boba
+
+    m = src.numel()
+    dev = src.device
+    rp = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    col = torch.empty(m, dtype=torch.int32, device=dev)
+    vv = torch.empty(m, dtype=torch.float32, device=dev)
+    y = torch.empty(n, dtype=torch.float32, device=dev)
+    s2, d2 = torch.empty_like(src), torch.empty_like(dst)
+    perm = torch.empty(n, dtype=torch.int32, device=dev)
+    order = torch.empty(n, dtype=torch.int32, device=dev)
+    ws_r = torch.empty(max(1, boba.boba_reorder_workspace(n, m)), dtype=torch.uint8, device=dev)
+    ws_c = torch.empty(max(1, boba.coo_to_csr_workspace(n, m)), dtype=torch.uint8, device=dev)
+    ws_s = torch.empty(max(1, boba.spmv_csr_workspace(n, m)), dtype=torch.uint8, device=dev)
+    t = {k: [] for k in ("csr_in", "spmv_in", "reorder", "relabel", "csr_boba", "spmv_boba")}
+    for _ in range(reps + 1):  # first round warms up
+        e = _events(torch, 8)
+        e[0].record()
+        boba.coo_to_csr(src, dst, val, n, ws=ws_c, out=(rp, col, vv))
+        e[1].record()
+        boba.spmv_csr(rp, col, vv, x, y=y, ws=ws_s)
+        e[2].record()
+        boba.boba_reorder(src, dst, n, ws=ws_r, perm=perm, order=order)
+        e[3].record()
+        boba.boba_relabel(src, dst, perm, src_out=s2, dst_out=d2)
+        e[4].record()
+        boba.coo_to_csr(s2, d2, val, n, ws=ws_c, out=(rp, col, vv))
+        e[5].record()
+        boba.spmv_csr(rp, col, vv, x, y=y, ws=ws_s)  # x in any labelling: same access pattern cost
+        e[6].record()
+        torch.cuda.synchronize()
+        for i, k in enumerate(t):
+            t[k].append(e[i].elapsed_time(e[i + 1]))
+    med = {k: float(np.median(v[1:])) for k, v in t.items()}
+    med["never"] = med["csr_in"] + spmv_iters * med["spmv_in"]
+    med["always"] = med["reorder"] + med["relabel"] + med["csr_boba"] + spmv_iters * med["spmv_boba"]
+    return med
+
+
+# ------------------------------------------------------------------- dataset
+def selector_specs(count, seed, log2_lo=10.0, log2_hi=18.0):
+    """Graphs from the batch families (RMAT / RGG, random labels)."""
+    return graphgen.batch_specs(count, seed=seed, log2_lo=log2_lo, log2_hi=log2_hi)
+
+
+def build_dataset(specs, *, reps=5, log=None, workers=0):
+    """Features (GPU kernel), both path timings and the label for every spec.
+    Graphs are generated in chunks (before each chunk's GPU work)."""
+    import torch
+
+    from . import boba
+
+    dev = torch.device("cuda:0")
+    X = np.zeros((len(specs), N_FEAT), np.float32)
+    rows = []
+    ws_f = torch.empty(boba.load().boba_graph_features_workspace(), dtype=torch.uint8, device=dev)
+    chunk = 64
+    for c0 in range(0, len(specs), chunk):
+        part = specs[c0:c0 + chunk]
+        graphs = [graphgen.make_batch_graph(s) for s in part]
+        for j, (s, (src_h, dst_h)) in enumerate(zip(part, graphs)):
+            i = c0 + j
+            src = torch.from_numpy(src_h).to(dev)
+            dst = torch.from_numpy(dst_h).to(dev)
+            val = torch.from_numpy(graphgen.uniform_values(src_h.size, s.seed + 3)).to(dev)
+            x = torch.from_numpy(graphgen.uniform_values(s.n, s.seed + 4)).to(dev)
+            # feature + inference overhead as served
+            e = _events(torch, 2)
+            e[0].record()
+            f = boba.boba_graph_features(src, dst, s.n, ws=ws_f)
+            e[1].record()
+            torch.cuda.synchronize()
+            X[i] = f.cpu().numpy()
+            med = measure_paths(src, dst, val, x, s.n, reps=reps)
+            med["t_feat"] = e[0].elapsed_time(e[1])
+            med.update({"kind": s.kind, "n": s.n, "m": int(src_h.size), "seed": s.seed})
+            rows.append(med)
+        if log:
+            log(f"dataset {min(c0 + chunk, len(specs))}/{len(specs)}")
+    T_never = np.array([r["never"] for r in rows])
+    T_always = np.array([r["always"] for r in rows])
+    y = np.log2(T_never / T_always).astype(np.float32)
+    return X, y, rows
+
+
+# --------------------------------------------------------------------- model
+def init_params(seed):
+    """He-style initialisation of the 16-64-64-1 network (float32)."""
+    rng = np.random.default_rng(seed)
+    parts = [rng.normal(0, np.sqrt(2 / 16), (64, 16)), np.zeros(64),
+             rng.normal(0, np.sqrt(2 / 64), (64, 64)), np.zeros(64),
+             rng.normal(0, np.sqrt(1 / 64), (1, 64)), np.zeros(1)]
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+
+
+def fold_standardisation(params, mu, sigma):
+    """Returns parameters that take raw features: W1' = W1 / sigma,
+    b1' = b1 - W1' mu."""
+    p = params.astype(np.float64).copy()
+    W1 = p[:1024].reshape(64, 16)
+    b1 = p[1024:1088]
+    W1n = W1 / sigma[None, :]
+    p[1024:1088] = b1 - W1n @ mu
+    p[:1024] = W1n.ravel()
+    return p.astype(np.float32)
+
+
+def train(X, y, *, epochs=200, batch=256, lr=1e-3, seed=0, log=None):
+    """Adam on mean squared error with the library's kernels.  Returns
+    (deployable params on raw features, mu, sigma, loss history)."""
+    import torch
+
+    from . import boba
+
+    dev = torch.device("cuda:0")
+    mu = X.mean(axis=0).astype(np.float64)
+    sigma = X.std(axis=0).astype(np.float64)
+    sigma[sigma < 1e-6] = 1.0
+    Xs = ((X - mu) / sigma).astype(np.float32)
+    Xd = torch.from_numpy(Xs).to(dev)
+    yd = torch.from_numpy(y.astype(np.float32)).to(dev)
+    p = torch.from_numpy(init_params(seed)).to(dev)
+    m1, m2 = torch.zeros_like(p), torch.zeros_like(p)
+    grad = torch.empty_like(p)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    rng = np.random.default_rng(seed + 1)
+    N = X.shape[0]
+    step = 0
+    hist = []
+    for ep in range(epochs):
+        idx = rng.permutation(N)
+        for b0 in range(0, N, batch):
+            sel = torch.from_numpy(idx[b0:b0 + batch]).to(dev)
+            xb = Xd.index_select(0, sel).contiguous()
+            yb = yd.index_select(0, sel).contiguous()
+            boba.boba_mlp_backward(p, xb, yb, grad=grad, loss=loss)
+            step += 1
+            boba.boba_mlp_adam(p, m1, m2, grad, step, lr=lr)
+        if ep % max(1, epochs // 10) == 0 or ep == epochs - 1:
+            _, full = boba.boba_mlp_backward(p, Xd, yd)
+            hist.append(float(full.cpu()[0]))
+            if log:
+                log(f"epoch {ep}: train mse {hist[-1]:.4f}")
+    return fold_standardisation(p.cpu().numpy(), mu, sigma), mu, sigma, hist
+
+
+# ----------------------------------------------------------------- selector
+def _digest(arrays):
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()
+
+
+def save_model(path, params, mu, sigma, meta=None):
+    np.savez(path, params=params.astype(np.float32), mu=mu, sigma=sigma, version=np.array([1]),
+             checksum=np.frombuffer(_digest([params.astype(np.float32), mu, sigma]).encode(), np.uint8),
+             meta=np.frombuffer(json.dumps(meta or {}).encode(), np.uint8))
+
+
+def load_model(path):
+    """Returns params (float32[5313]) or None if the file is missing or invalid."""
+    try:
+        z = np.load(path, allow_pickle=False)
+        params, mu, sigma = z["params"], z["mu"], z["sigma"]
+        ok = (int(z["version"][0]) == 1 and params.shape == (5313,) and params.dtype == np.float32
+              and bytes(z["checksum"]).decode() == _digest([params, mu, sigma]) and np.all(np.isfinite(params)))
+        return params if ok else None
+    except Exception:
+        return None
+
+
+class Selector:
+    """decide(src, dst, n) -> (reorder?, prediction).  Falls back to always
+    reordering when there is no usable model or the inputs are not finite."""
+
+    def __init__(self, params=None, device="cuda:0"):
+        import torch
+
+        from . import boba
+
+        self.boba = boba
+        self.dev = torch.device(device)
+        self.params = None if params is None else torch.from_numpy(np.asarray(params, np.float32)).to(self.dev)
+        self.ws = torch.empty(boba.load().boba_graph_features_workspace(), dtype=torch.uint8, device=self.dev)
+        self.feat = torch.empty(1, N_FEAT, dtype=torch.float32, device=self.dev)
+        self.out = torch.empty(1, dtype=torch.float32, device=self.dev)
+
+    @classmethod
+    def from_file(cls, path, device="cuda:0"):
+        return cls(load_model(path), device)
+
+    def decide(self, src, dst, n):
+        if self.params is None:
+            return True, float("nan")
+        self.boba.boba_graph_features(src, dst, n, out=self.feat.view(-1), ws=self.ws)
+        self.boba.boba_mlp_forward(self.params, self.feat, out=self.out)
+        pred = float(self.out.cpu()[0])
+        if not np.isfinite(pred):
+            return True, pred
+        return pred > 0.0, pred
+
+
+def evaluate(params, X, rows, t_infer_ms):
+    """Held-out totals: the selector's choice (plus its feature and inference
+    time) against the oracle choice, always-reorder and never-reorder."""
+    import torch
+
+    from . import boba
+
+    dev = torch.device("cuda:0")
+    pred = boba.boba_mlp_forward(torch.from_numpy(params).to(dev), torch.from_numpy(X).to(dev)).cpu().numpy()
+    never = np.array([r["never"] for r in rows])
+    always = np.array([r["always"] for r in rows])
+    feat = np.array([r["t_feat"] for r in rows])
+    choose = np.where(np.isfinite(pred), pred > 0, True)
+    chosen = np.where(choose, always, never)
+    opt = np.minimum(never, always)
+    sel_total = float(np.sum(feat + t_infer_ms + chosen))
+    return {"graphs": len(rows), "selector_ms": sel_total, "oracle_choice_ms": float(opt.sum()),
+            "always_ms": float(always.sum()), "never_ms": float(never.sum()),
+            "selector_vs_oracle": sel_total / float(opt.sum()),
+            "selector_vs_always": sel_total / float(always.sum()),
+            "decisions_reorder": int(choose.sum()), "oracle_reorder": int((always < never).sum()),
+            "agreement": float(np.mean(choose == (always < never)))}
+
+
+def time_inference(params, reps=50):
+    """Median ms of one MLP forward for one graph plus the host read-back."""
+    import torch
+
+    from . import boba
+
+    dev = torch.device("cuda:0")
+    p = torch.from_numpy(params).to(dev)
+    f = torch.zeros(1, N_FEAT, dtype=torch.float32, device=dev)
+    out = torch.empty(1, dtype=torch.float32, device=dev)
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        boba.boba_mlp_forward(p, f, out=out)
+        float(out.cpu()[0])
+        ts.append((time.perf_counter() - t0) * 1e3)
+    return float(np.median(ts))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description="train and evaluate the reorder selector on the GPU")
+    ap.add_argument("--train", type=int, default=4000)
+    ap.add_argument("--heldout", type=int, default=500)
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--epochs", type=int, default=200)
+    ap.add_argument("--log2-hi", type=float, default=18.0)
+    ap.add_argument("--out", default="gpurun_out/selector_model.npz")
+    ap.add_argument("--data-out", default="gpurun_out/selector_data.npz")
+    args = ap.parse_args(argv)
+    log = lambda s: print(f"[selector] {s}", file=sys.stderr, flush=True)
+    tr_specs = selector_specs(args.train, graphgen.BASE_SEED + 50, log2_hi=args.log2_hi)
+    ho_specs = selector_specs(args.heldout, graphgen.BASE_SEED + 51, log2_hi=args.log2_hi)
+    t0 = time.perf_counter()
+    Xtr, ytr, rtr = build_dataset(tr_specs, reps=args.reps, log=log)
+    Xho, yho, rho = build_dataset(ho_specs, reps=args.reps, log=log)
+    log(f"datasets in {time.perf_counter() - t0:.1f}s; train labels: {np.mean(ytr > 0):.3f} reorder-pays")
+    params, mu, sigma, hist = train(Xtr, ytr, epochs=args.epochs, log=log)
+    os.makedirs(os.path.dirname(args.out) or ".", exist_ok=True)
+    save_model(args.out, params, mu, sigma, {"train": args.train, "epochs": args.epochs})
+    np.savez(args.data_out, Xtr=Xtr, ytr=ytr, Xho=Xho, yho=yho,
+             rows_tr=np.frombuffer(json.dumps(rtr).encode(), np.uint8),
+             rows_ho=np.frombuffer(json.dumps(rho).encode(), np.uint8))
+    t_inf = time_inference(params)
+    res = evaluate(params, Xho, rho, t_inf)
+    res.update({"train_graphs": args.train, "train_mse": hist[-1], "t_infer_ms": t_inf,
+                "t_feat_ms_median": float(np.median([r["t_feat"] for r in rho]))})
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
