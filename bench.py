@@ -46,6 +46,8 @@ def kernel_alg_bytes(name, n, m):
         "spmv": 8 * m + 4 * (n + 1) + 8 * n,   # val, col, rowptr, x once, y
         "bucket_split": 16 * m,                # read src, dst; write one record each
         "bucket_min": 8 * m + 4 * n,           # read the records; write r
+        "bucket_relabel": 16 * m + 4 * n,      # read the records, perm; write new IDs
+        "tile_unsplit": 24 * m,                # read records and new IDs; write src', dst'
         "rank": 12 * n,                        # read r, write perm, order
         "mark": 4 * n,                         # read r (bitmap writes are ours)
     }
@@ -192,24 +194,22 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    stage_names = ["reorder", "relabel", "coo_to_csr", "spmv"]
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    stage_names = ["reorder_relabel", "coo_to_csr", "spmv"]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    ws_rr = torch.empty(boba.boba_reorder_relabel_workspace(n, m), dtype=torch.uint8, device=dev)
 
     def step(e=None):
         if e:
             e[0].record()
-        boba.boba_reorder(src, dst, n, ws=ws_r, perm=perm, order=order)
+        boba.boba_reorder_relabel(src, dst, n, ws=ws_rr, perm=perm, order=order, src_out=s2, dst_out=d2)
         if e:
             e[1].record()
-        boba.boba_relabel(src, dst, perm, src_out=s2, dst_out=d2)
-        if e:
-            e[2].record()
         boba.coo_to_csr(s2, d2, val, n, ws=ws_c, out=(rowptr, col, val_c))
         if e:
-            e[3].record()
+            e[2].record()
         boba.spmv_csr(rowptr, col, val_c, x2, y=y, ws=ws_s)
         if e:
-            e[4].record()
+            e[3].record()
 
     # x in the new labelling, so the reordered product equals the original one
     boba.boba_reorder(src, dst, n, ws=ws_r, perm=perm, order=order)
@@ -230,11 +230,22 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kern = boba.boba_timing_collect()
-    boba.boba_timing_enable(False)
     stage_ms = {name: float(np.mean([ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(args.steps)]))
                 for i, name in enumerate(stage_names)}
     ms_per_step = wall * 1e3 / args.steps
     log(f"{ms_per_step:.3f} ms/step; stages {stage_ms}")
+
+    # the reorder alone (the metric's edges/s): boba_reorder timed the same number of times
+    er = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+    for k in range(args.steps):
+        er[k][0].record()
+        boba.boba_reorder(src, dst, n, ws=ws_r, perm=perm, order=order)
+        er[k][1].record()
+    torch.cuda.synchronize()
+    reorder_kern = boba.boba_timing_collect()
+    boba.boba_timing_enable(False)
+    stage_ms["reorder"] = float(np.mean([er[k][0].elapsed_time(er[k][1]) for k in range(args.steps)]))
+    log(f"boba_reorder alone: {stage_ms['reorder']:.3f} ms")
 
     # SpMV and CSR build on the input labelling ("before")
     log("before-reorder leg")
@@ -261,17 +272,17 @@ def main():
     assert boba.boba_check_device_error() == boba.BOBA_OK
 
     kernels = {}
-    for name, (tot, cnt) in kern.items():
+    for name, (tot, cnt) in list(kern.items()) + [(f"{k} [boba_reorder alone]", v) for k, v in reorder_kern.items()]:
         per_step = cnt / args.steps
         avg = tot / cnt
         entry = {"avg_ms": avg, "launches_per_step": per_step, "ms_per_step": tot / args.steps}
-        ab = kernel_alg_bytes(name, n, m)
+        ab = kernel_alg_bytes(name.split(" [")[0], n, m)
         if ab is not None:
             entry["alg_bytes_per_launch"] = ab
             entry["achieved_GBs"] = ab / (avg * 1e-3) / 1e9
             entry["hbm_frac"] = entry["achieved_GBs"] / HBM_PEAK_GBS
         kernels[name] = entry
-    dom = max((k for k in kernels if "alg_bytes_per_launch" in kernels[k]),
+    dom = max((k for k in kernels if "alg_bytes_per_launch" in kernels[k] and "[" not in k),
               key=lambda k: kernels[k]["ms_per_step"])
     dk = kernels[dom]
     traffic = pmc_traffic(dom, args.workload, dk["launches_per_step"])
@@ -303,7 +314,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "m": m,
                    "generator": _describe(args.workload),
-                   "step": "boba_reorder -> boba_relabel -> coo_to_csr -> spmv_csr"},
+                   "step": "boba_reorder_relabel -> coo_to_csr -> spmv_csr",
+                   "value": "m / duration of boba_reorder alone (mean of --steps calls, HIP events)"},
         "reorder_ms": reorder_ms,
         "reorder_hbm_frac_alg": reorder_alg / (reorder_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "path_edges_per_s": m / (ms_per_step * 1e-3),

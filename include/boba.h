@@ -89,6 +89,19 @@ BOBA_API boba_status boba_relabel(const int32_t *src, const int32_t *dst, int64_
                          const int32_t *perm, int64_t n, int32_t *src_out, int32_t *dst_out,
                          hipStream_t stream);
 
+/* ------------------------------------------------- reorder + relabel ---
+ * boba_reorder followed by boba_relabel in one call (same results as the two
+ * calls).  For graphs up to 2^25 vertices with 16-byte aligned src/dst, the
+ * relabel reuses the reorder's vertex-bucketed copy of the edge list instead
+ * of gathering perm[] once per endpoint.  src_out / dst_out may equal src / dst
+ * (in place); other overlaps are not allowed.
+ *   ws  at least boba_reorder_relabel_workspace(n, m) bytes, 256-byte aligned.
+ * Errors: as boba_reorder. */
+BOBA_API size_t boba_reorder_relabel_workspace(int64_t n, int64_t m);
+BOBA_API boba_status boba_reorder_relabel(const int32_t *src, const int32_t *dst, int64_t m, int64_t n,
+                                          int32_t *perm, int32_t *order, int32_t *src_out, int32_t *dst_out,
+                                          void *ws, size_t ws_bytes, uint32_t flags, hipStream_t stream);
+
 /* ---------------------------------------------------------- COO -> CSR ---
  * Builds CSR from COO (the conversion of Sec. 1.1 and Sec. 5.3) by a stable
  * sort on the row: rowptr[r] = #{k : row[k] < r}, and within each row the

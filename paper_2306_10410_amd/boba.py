@@ -28,6 +28,8 @@ PROTOTYPES = {
     "boba_reorder_workspace": (_SZ, [_I64, _I64]),
     "boba_reorder": (_I32, [_P, _P, _I64, _I64, _P, _P, _P, _SZ, _U32, _P]),
     "boba_relabel": (_I32, [_P, _P, _I64, _P, _I64, _P, _P, _P]),
+    "boba_reorder_relabel_workspace": (_SZ, [_I64, _I64]),
+    "boba_reorder_relabel": (_I32, [_P, _P, _I64, _I64, _P, _P, _P, _P, _P, _SZ, _U32, _P]),
     "coo_to_csr_workspace": (_SZ, [_I64, _I64]),
     "coo_to_csr": (_I32, [_P, _P, _P, _I64, _I64, _P, _P, _P, _P, _SZ, _P]),
     "spmv_csr_workspace": (_SZ, [_I64, _I64]),
@@ -132,6 +134,30 @@ def boba_relabel(src, dst, perm, *, src_out=None, dst_out=None, stream=None):
     _check(load().boba_relabel(_ptr(src), _ptr(dst), src.numel(), _ptr(perm), perm.numel(), _ptr(src_out),
                                _ptr(dst_out), _stream(stream)))
     return src_out, dst_out
+
+
+def boba_reorder_relabel_workspace(n: int, m: int) -> int:
+    return int(load().boba_reorder_relabel_workspace(n, m))
+
+
+def boba_reorder_relabel(src, dst, n: int, *, with_order: bool = True, flags: int = 0, ws=None, perm=None,
+                         order=None, src_out=None, dst_out=None, stream=None):
+    """Returns (perm, order, src_out, dst_out)."""
+    _dev_i32(src, "src")
+    _dev_i32(dst, "dst")
+    m = src.numel()
+    if dst.numel() != m:
+        raise ValueError("src and dst differ in length")
+    dev = src.device
+    perm = torch.empty(n, dtype=torch.int32, device=dev) if perm is None else perm
+    if with_order and order is None:
+        order = torch.empty(n, dtype=torch.int32, device=dev)
+    src_out = torch.empty_like(src) if src_out is None else src_out
+    dst_out = torch.empty_like(dst) if dst_out is None else dst_out
+    ws = _workspace(boba_reorder_relabel_workspace(n, m), dev, ws)
+    _check(load().boba_reorder_relabel(_ptr(src), _ptr(dst), m, n, _ptr(perm), _ptr(order) if with_order else None,
+                                       _ptr(src_out), _ptr(dst_out), _ptr(ws), ws.numel(), flags, _stream(stream)))
+    return perm, (order if with_order else None), src_out, dst_out
 
 
 def coo_to_csr_workspace(n_rows: int, m: int) -> int:

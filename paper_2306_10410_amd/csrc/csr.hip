@@ -17,27 +17,39 @@
 namespace boba {
 namespace {
 
-constexpr int kBlock = 256;
+constexpr int kBlock = 512;
 constexpr int kNWave = kBlock / kWave;
 constexpr int kItems = 16;
-constexpr uint32_t kTile = kBlock * kItems;       // edges per workgroup
+constexpr uint32_t kTile = kBlock * kItems;       // 8192 edges per workgroup: ~128-byte digit runs
 constexpr uint32_t kWaveRun = kWave * kItems;     // contiguous edges per wave
 
 template <int BITS>
 __global__ __launch_bounds__(kBlock) void k_radix_hist(const int32_t *__restrict__ keys, uint32_t m, uint32_t shift,
                                                        uint32_t tiles, uint32_t *__restrict__ hist) {
     constexpr uint32_t BINS = 1u << BITS;
-    __shared__ uint32_t h[BINS];
-    for (uint32_t d = threadIdx.x; d < BINS; d += kBlock) h[d] = 0;
+    // one sub-histogram per wave: skewed digits (hub rows) contend less
+    __shared__ uint32_t h[kNWave][BINS];
+    for (uint32_t d = threadIdx.x; d < kNWave * BINS; d += kBlock) (&h[0][0])[d] = 0;
     __syncthreads();
     const uint32_t base = blockIdx.x * kTile + threadIdx.x;
+    const uint32_t wave = threadIdx.x / kWave;
+    uint32_t k[kItems];
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
-        uint32_t i = base + j * kBlock;
-        if (i < m) atomicAdd(&h[((uint32_t)keys[i] >> shift) & (BINS - 1)], 1u);
+        const uint32_t i = base + j * kBlock;
+        k[j] = i < m ? (uint32_t)keys[i] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        if (base + j * kBlock < m) atomicAdd(&h[wave][(k[j] >> shift) & (BINS - 1)], 1u);
     }
     __syncthreads();
-    for (uint32_t d = threadIdx.x; d < BINS; d += kBlock) hist[d * tiles + blockIdx.x] = h[d];
+    for (uint32_t d = threadIdx.x; d < BINS; d += kBlock) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int w = 0; w < kNWave; ++w) t += h[w][d];
+        hist[d * tiles + blockIdx.x] = t;
+    }
 }
 
 template <int BITS, bool HAS_VAL>
@@ -51,8 +63,9 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const int32_t *__restr
                                                           float *__restrict__ val_out) {
     constexpr uint32_t BINS = 1u << BITS;
     constexpr uint32_t MASK = BINS - 1;
-    constexpr uint32_t DPT = BINS / kBlock;  // digits per thread in the tile scan
-    static_assert(BINS % kBlock == 0, "need at least 8 digit bits");
+    // digits per thread in the tile scan (threads beyond BINS hold none)
+    constexpr uint32_t DPT = BINS >= (uint32_t)kBlock ? BINS / kBlock : 1;
+    static_assert(BINS % kBlock == 0 || kBlock % BINS == 0, "digit count and block size must divide");
     __shared__ uint32_t s_cnt[kNWave][BINS];  // per-wave counts, then run starts
     __shared__ uint32_t s_gofs[BINS];
     __shared__ uint32_t s_start[BINS];
@@ -97,10 +110,12 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const int32_t *__restr
 
     // Tile-local start of every (digit, wave) run, digit-major.
     {
+        const bool owns = threadIdx.x * DPT < BINS;
         uint32_t s = 0;
 #pragma unroll
         for (uint32_t q = 0; q < DPT; ++q) {
             const uint32_t d = threadIdx.x * DPT + q;
+            if (!owns) break;
 #pragma unroll
             for (int w = 0; w < kNWave; ++w) s += s_cnt[w][d];
         }
@@ -109,6 +124,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const int32_t *__restr
 #pragma unroll
         for (uint32_t q = 0; q < DPT; ++q) {
             const uint32_t d = threadIdx.x * DPT + q;
+            if (!owns) break;
             s_start[d] = run;
 #pragma unroll
             for (int w = 0; w < kNWave; ++w) {

@@ -234,7 +234,7 @@ constexpr uint32_t kBucketW = 1u << kVBits;                     // vertices per 
 constexpr uint32_t kMaxBuckets = 1024;                          // LDS budget of split
 constexpr uint32_t kSentinel = 0xFFFFFFFFu;
 constexpr int kMinThreads = 1024;
-constexpr int kMinGroup = 8;                                    // tiles per wave step
+constexpr int kMinGroup = 16;                                   // segments in flight per wave
 
 inline uint32_t split_region(uint32_t nb) { return (kTileT + 3 * nb + 3) & ~3u; }
 
@@ -413,6 +413,108 @@ __global__ __launch_bounds__(kMinThreads) void k_bucket_min(const uint32_t *__re
     for (uint32_t i = threadIdx.x; i < cnt; i += kMinThreads) o[i] = lr[i];
 }
 
+
+// -------------------------------------------------- fused relabel (bucketed)
+// After the ranks are known, the split's records relabel the edges without a
+// random perm gather per endpoint:
+//   bucket_relabel  workgroup (bucket, slice): perm of the bucket's vertices in
+//                   LDS; every record of the bucket gets its new ID, written
+//                   to `vals` in the record's own slot (coalesced).
+//   tile_unsplit    workgroup per tile: scatters the tile's new IDs back to
+//                   element order in LDS, then writes them out coalesced.
+__global__ __launch_bounds__(kMinThreads) void k_bucket_relabel(const uint32_t *__restrict__ recs,
+                                                                const uint32_t *__restrict__ off_t, uint32_t nt,
+                                                                uint32_t region, uint32_t nb, uint32_t tps,
+                                                                uint32_t batch, uint32_t n,
+                                                                const int32_t *__restrict__ perm,
+                                                                uint32_t *__restrict__ vals) {
+    __shared__ uint32_t lp[kBucketW];
+    const uint32_t b = blockIdx.x % nb;
+    const uint32_t s = blockIdx.x / nb;
+    const uint32_t t0 = s * tps;
+    const uint32_t t1 = min(nt, t0 + tps);
+    const uint32_t cntv = min(kBucketW, n - b * kBucketW);
+    for (uint32_t i = threadIdx.x; i < cntv; i += kMinThreads) lp[i] = (uint32_t)perm[(size_t)b * kBucketW + i];
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wave = threadIdx.x / kWave;
+    constexpr uint32_t NWAVE = kMinThreads / kWave;
+    const uint32_t *beg = off_t + (size_t)b * nt;
+    const uint32_t *end = off_t + (size_t)(b + 1) * nt;
+    for (uint32_t tb = t0 + wave * batch; tb < t1; tb += NWAVE * batch) {
+        const uint32_t cnt = min(batch, t1 - tb);
+        const uint32_t sb = lane < cnt ? beg[tb + lane] : 0u;
+        const uint32_t se = lane < cnt ? end[tb + lane] : 0u;
+        for (uint32_t g0 = 0; g0 < cnt; g0 += kMinGroup) {
+            uint2 x[kMinGroup];
+            uint32_t kk[kMinGroup];
+#pragma unroll
+            for (int g = 0; g < kMinGroup; ++g) {
+                const uint32_t gi = g0 + g;
+                const uint32_t b0 = __shfl(sb, gi & (kWave - 1), kWave);
+                const uint32_t e0 = __shfl(se, gi & (kWave - 1), kWave);
+                kk[g] = b0 + 2 * lane;
+                x[g] = (gi < cnt && kk[g] < e0) ? *(const uint2 *)(recs + (size_t)(tb + gi) * region + kk[g])
+                                                : make_uint2(kSentinel, kSentinel);
+            }
+#pragma unroll
+            for (int g = 0; g < kMinGroup; ++g) {
+                const uint32_t gi = g0 + g;
+                const uint32_t tile = tb + gi;
+                const uint32_t e0 = __shfl(se, gi & (kWave - 1), kWave);
+                uint32_t k = kk[g];
+                uint2 r2 = x[g];
+                while (gi < cnt && k < e0) {
+                    uint2 v;
+                    v.x = r2.x != kSentinel ? lp[r2.x & (kBucketW - 1)] : kSentinel;
+                    v.y = r2.y != kSentinel ? lp[r2.y & (kBucketW - 1)] : kSentinel;
+                    *(uint2 *)(vals + (size_t)tile * region + k) = v;
+                    k += 2 * kWave;
+                    if (k >= e0) break;  // segments longer than 128 records (rare)
+                    r2 = *(const uint2 *)(recs + (size_t)tile * region + k);
+                }
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kSplitThreads) void k_tile_unsplit(const uint32_t *__restrict__ recs,
+                                                                 const uint32_t *__restrict__ vals,
+                                                                 const uint32_t *__restrict__ tile_off, uint32_t nb,
+                                                                 uint32_t region, uint32_t m, uint32_t tiles_half,
+                                                                 int32_t *__restrict__ src_out,
+                                                                 int32_t *__restrict__ dst_out) {
+    __shared__ __align__(16) uint32_t out[kTileT];
+    // elements without a record (out-of-range IDs) come out as -1
+    for (uint32_t i = threadIdx.x; i < kTileT; i += kSplitThreads) out[i] = kSentinel;
+    __syncthreads();
+    const uint32_t t = blockIdx.x;
+    const bool h = t >= tiles_half;
+    const uint32_t k0 = (t - (h ? tiles_half : 0u)) * kTileT;
+    const uint32_t total = tile_off[(size_t)t * (nb + 1) + nb];
+    const v4u *r4 = (const v4u *)(recs + (size_t)t * region);
+    const v4u *v4 = (const v4u *)(vals + (size_t)t * region);
+    for (uint32_t i = threadIdx.x; i < total / 4; i += kSplitThreads) {
+        const v4u r = __builtin_nontemporal_load(&r4[i]);
+        const v4u v = __builtin_nontemporal_load(&v4[i]);
+        if (r.x != kSentinel) out[r.x >> kVBits] = v.x;
+        if (r.y != kSentinel) out[r.y >> kVBits] = v.y;
+        if (r.z != kSentinel) out[r.z >> kVBits] = v.z;
+        if (r.w != kSentinel) out[r.w >> kVBits] = v.w;
+    }
+    __syncthreads();
+    int32_t *o = (h ? dst_out : src_out) + k0;
+    const uint32_t count = min(kTileT, m - k0);
+    if ((((uintptr_t)o) & 15u) == 0) {
+        const v4i *o4s = (const v4i *)out;
+        for (uint32_t i = threadIdx.x; i < count / 4; i += kSplitThreads)
+            __builtin_nontemporal_store(o4s[i], (v4i *)o + i);
+        for (uint32_t i = (count & ~3u) + threadIdx.x; i < count; i += kSplitThreads) o[i] = (int32_t)out[i];
+    } else {
+        for (uint32_t i = threadIdx.x; i < count; i += kSplitThreads) o[i] = (int32_t)out[i];
+    }
+}
+
 // mark with the merge of slice minima: r[v] = min over slices, then set the
 // bitmap bit of key(v).
 __global__ __launch_bounds__(kBlock) void k_mark_merge(uint32_t *__restrict__ rpart, uint32_t slices, uint32_t n,
@@ -458,11 +560,12 @@ struct ReorderLayout {
     uint2 *W;
     uint32_t *partial;
     uint32_t *recs, *tile_off, *off_t;
+    uint32_t *vals;  // new IDs in record layout (fused relabel only)
     size_t bytes;
     uint32_t nw;
 };
 
-ReorderLayout reorder_layout(void *ws, int64_t n, int64_t m, const ReorderPlan &P) {
+ReorderLayout reorder_layout(void *ws, int64_t n, int64_t m, const ReorderPlan &P, bool with_vals = false) {
     ReorderLayout L;
     const uint64_t positions = 2 * (uint64_t)m + (uint64_t)n;
     L.nw = ceil_div(positions, 32);
@@ -473,8 +576,16 @@ ReorderLayout reorder_layout(void *ws, int64_t n, int64_t m, const ReorderPlan &
     L.recs = c.take<uint32_t>(P.bucketed ? (size_t)P.nt * P.region : 0);
     L.tile_off = c.take<uint32_t>(P.bucketed ? (size_t)P.nt * (P.nb + 1) : 0);
     L.off_t = c.take<uint32_t>(P.bucketed ? (size_t)P.nt * (P.nb + 1) : 0);
+    L.vals = c.take<uint32_t>(P.bucketed && with_vals ? (size_t)P.nt * P.region : 0);
     L.bytes = c.bytes();
     return L;
+}
+
+// Tiles per wave step of the bucket kernels: spread a slice's tiles over all 16 waves.
+uint32_t min_batch(const ReorderPlan &P) {
+    uint32_t batch = ceil_div(P.tps, kMinThreads / kWave);
+    batch = (batch + kMinGroup - 1) / kMinGroup * kMinGroup;
+    return batch < (uint32_t)kMinGroup ? kMinGroup : (batch > (uint32_t)kWave ? kWave : batch);
 }
 
 boba_status check_sizes(int64_t m, int64_t n, bool positions) {
@@ -486,39 +597,13 @@ boba_status check_sizes(int64_t m, int64_t n, bool positions) {
     return BOBA_OK;
 }
 
-}  // namespace
-}  // namespace boba
-
-using namespace boba;
-
-extern "C" size_t boba_reorder_workspace(int64_t n, int64_t m) {
-    if (n < 0 || m < 0) return 0;
-    return reorder_layout(nullptr, n, m, reorder_plan(n, m)).bytes;
-}
-
-extern "C" boba_status boba_reorder(const int32_t *src, const int32_t *dst, int64_t m, int64_t n, int32_t *perm,
-                                    int32_t *order, void *ws, size_t ws_bytes, uint32_t flags, hipStream_t stream) {
-    clear_error();
-    if (boba_status e = check_sizes(m, n, true)) return e;
-    if (flags & ~BOBA_FLAG_INTERLEAVED) return fail(BOBA_ERR_ARG, "boba_reorder: unknown flags 0x%x", flags);
-    if (m > 0 && (!src || !dst)) return fail(BOBA_ERR_ARG, "boba_reorder: src/dst is NULL");
-    if (m > 0 && n == 0) return fail(BOBA_ERR_ARG, "boba_reorder: edges given but n = 0");
-    if (n == 0) return BOBA_OK;
-    if (!perm) return fail(BOBA_ERR_ARG, "boba_reorder: perm is NULL");
-    const size_t need = boba_reorder_workspace(n, m);
-    if (!ws || ws_bytes < need || ((uintptr_t)ws & 255u))
-        return fail(BOBA_ERR_WORKSPACE, "boba_reorder: workspace needs %zu bytes, 256-byte aligned (got %zu at %p)",
-                    need, ws_bytes, ws);
-    int32_t *flag = range_flag();
-    if (!flag) return BOBA_ERR_HIP;
-
-    const bool inter = flags & BOBA_FLAG_INTERLEAVED;
-    const uint32_t un = (uint32_t)n, um = (uint32_t)m;
-    const ReorderPlan P = reorder_plan(n, m);
-    const ReorderLayout L = reorder_layout(ws, n, m, P);
+// Launches the reorder; *bucketed tells which scatter path ran.
+boba_status reorder_run(const int32_t *src, const int32_t *dst, uint32_t um, uint32_t un, int32_t *perm,
+                        int32_t *order, bool inter, const ReorderPlan &P, const ReorderLayout &L, int32_t *flag,
+                        hipStream_t stream, bool *bucketed_out) {
     const bool bucketed = P.bucketed && aligned16(src) && aligned16(dst);
+    *bucketed_out = bucketed;
     const uint32_t tail = 2 * um;
-
     if (bucketed) {
         BOBA_LAUNCH("reorder_init", k_reorder_init, dim3(grid_for(L.nw, kBlock * 4)), dim3(kBlock), stream, L.r, 0u,
                     L.W, L.nw);
@@ -526,20 +611,16 @@ extern "C" boba_status boba_reorder(const int32_t *src, const int32_t *dst, int6
                     P.tiles_half, un, P.nb, P.region, L.recs, L.tile_off, flag);
         BOBA_LAUNCH("bucket_transpose", k_transpose, dim3(ceil_div(P.nb + 1, 32), ceil_div(P.nt, 32)), dim3(256),
                     stream, (const uint32_t *)L.tile_off, P.nt, P.nb + 1, L.off_t);
-        // tiles per wave step: spread a slice's tiles over all 16 waves
-        uint32_t batch = ceil_div(P.tps, kMinThreads / kWave);
-        batch = (batch + kMinGroup - 1) / kMinGroup * kMinGroup;
-        batch = batch < (uint32_t)kMinGroup ? kMinGroup : (batch > (uint32_t)kWave ? kWave : batch);
         BOBA_LAUNCH("bucket_min", k_bucket_min, dim3(P.nb * P.slices), dim3(kMinThreads), stream,
                     (const uint32_t *)L.recs, (const uint32_t *)L.off_t, P.nt, P.tiles_half, P.region, P.nb, P.tps,
-                    batch, un, inter ? 1u : um, inter ? 2u : 1u, L.r);
+                    min_batch(P), un, inter ? 1u : um, inter ? 2u : 1u, L.r);
         BOBA_LAUNCH("mark", k_mark_merge, dim3(grid_for(un, kBlock * 4)), dim3(kBlock), stream, L.r, P.slices, un,
                     tail, L.W);
     } else {
         BOBA_LAUNCH("reorder_init", k_reorder_init, dim3(grid_for(un > L.nw ? un : L.nw, kBlock * 4)),
                     dim3(kBlock), stream, L.r, un, L.W, L.nw);
         uint32_t k0 = 0;
-        if (m > 0 && aligned16(src) && aligned16(dst)) {
+        if (um > 0 && aligned16(src) && aligned16(dst)) {
             const uint32_t m4 = um / 4;
             if (m4 > 0) {
                 dim3 grid(ceil_div(2ull * m4, kScatterTile));
@@ -572,17 +653,8 @@ extern "C" boba_status boba_reorder(const int32_t *src, const int32_t *dst, int6
     return BOBA_OK;
 }
 
-extern "C" boba_status boba_relabel(const int32_t *src, const int32_t *dst, int64_t m, const int32_t *perm, int64_t n,
-                                    int32_t *src_out, int32_t *dst_out, hipStream_t stream) {
-    clear_error();
-    if (boba_status e = check_sizes(m, n, false)) return e;
-    if (m == 0) return BOBA_OK;
-    if (!src || !dst || !src_out || !dst_out || !perm)
-        return fail(BOBA_ERR_ARG, "boba_relabel: NULL pointer");
-    if (n == 0) return fail(BOBA_ERR_ARG, "boba_relabel: edges given but n = 0");
-    int32_t *flag = range_flag();
-    if (!flag) return BOBA_ERR_HIP;
-    const uint32_t um = (uint32_t)m, un = (uint32_t)n;
+boba_status relabel_run(const int32_t *src, const int32_t *dst, uint32_t um, const int32_t *perm, uint32_t un,
+                        int32_t *src_out, int32_t *dst_out, int32_t *flag, hipStream_t stream) {
     uint32_t k0 = 0;
     if (aligned16(src) && aligned16(dst) && aligned16(src_out) && aligned16(dst_out)) {
         const uint32_t m4 = um / 4;
@@ -597,4 +669,92 @@ extern "C" boba_status boba_relabel(const int32_t *src, const int32_t *dst, int6
                     src, dst, k0, um, perm, un, src_out, dst_out, flag);
     }
     return BOBA_OK;
+}
+
+boba_status reorder_args(const int32_t *src, const int32_t *dst, int64_t m, int64_t n, int32_t *perm, uint32_t flags,
+                         const char *who) {
+    if (boba_status e = check_sizes(m, n, true)) return e;
+    if (flags & ~BOBA_FLAG_INTERLEAVED) return fail(BOBA_ERR_ARG, "%s: unknown flags 0x%x", who, flags);
+    if (m > 0 && (!src || !dst)) return fail(BOBA_ERR_ARG, "%s: src/dst is NULL", who);
+    if (m > 0 && n == 0) return fail(BOBA_ERR_ARG, "%s: edges given but n = 0", who);
+    if (n > 0 && !perm) return fail(BOBA_ERR_ARG, "%s: perm is NULL", who);
+    return BOBA_OK;
+}
+
+}  // namespace
+}  // namespace boba
+
+using namespace boba;
+
+extern "C" size_t boba_reorder_workspace(int64_t n, int64_t m) {
+    if (n < 0 || m < 0) return 0;
+    return reorder_layout(nullptr, n, m, reorder_plan(n, m)).bytes;
+}
+
+extern "C" boba_status boba_reorder(const int32_t *src, const int32_t *dst, int64_t m, int64_t n, int32_t *perm,
+                                    int32_t *order, void *ws, size_t ws_bytes, uint32_t flags, hipStream_t stream) {
+    clear_error();
+    if (boba_status e = reorder_args(src, dst, m, n, perm, flags, "boba_reorder")) return e;
+    if (n == 0) return BOBA_OK;
+    const size_t need = boba_reorder_workspace(n, m);
+    if (!ws || ws_bytes < need || ((uintptr_t)ws & 255u))
+        return fail(BOBA_ERR_WORKSPACE, "boba_reorder: workspace needs %zu bytes, 256-byte aligned (got %zu at %p)",
+                    need, ws_bytes, ws);
+    int32_t *flag = range_flag();
+    if (!flag) return BOBA_ERR_HIP;
+    const ReorderPlan P = reorder_plan(n, m);
+    const ReorderLayout L = reorder_layout(ws, n, m, P);
+    bool bucketed = false;
+    return reorder_run(src, dst, (uint32_t)m, (uint32_t)n, perm, order, flags & BOBA_FLAG_INTERLEAVED, P, L, flag,
+                       stream, &bucketed);
+}
+
+extern "C" size_t boba_reorder_relabel_workspace(int64_t n, int64_t m) {
+    if (n < 0 || m < 0) return 0;
+    return reorder_layout(nullptr, n, m, reorder_plan(n, m), true).bytes;
+}
+
+extern "C" boba_status boba_reorder_relabel(const int32_t *src, const int32_t *dst, int64_t m, int64_t n,
+                                            int32_t *perm, int32_t *order, int32_t *src_out, int32_t *dst_out,
+                                            void *ws, size_t ws_bytes, uint32_t flags, hipStream_t stream) {
+    clear_error();
+    if (boba_status e = reorder_args(src, dst, m, n, perm, flags, "boba_reorder_relabel")) return e;
+    if (m > 0 && (!src_out || !dst_out)) return fail(BOBA_ERR_ARG, "boba_reorder_relabel: src_out/dst_out is NULL");
+    if (n == 0) return BOBA_OK;
+    const size_t need = boba_reorder_relabel_workspace(n, m);
+    if (!ws || ws_bytes < need || ((uintptr_t)ws & 255u))
+        return fail(BOBA_ERR_WORKSPACE,
+                    "boba_reorder_relabel: workspace needs %zu bytes, 256-byte aligned (got %zu at %p)", need, ws_bytes,
+                    ws);
+    int32_t *flag = range_flag();
+    if (!flag) return BOBA_ERR_HIP;
+    const uint32_t um = (uint32_t)m, un = (uint32_t)n;
+    const ReorderPlan P = reorder_plan(n, m);
+    const ReorderLayout L = reorder_layout(ws, n, m, P, true);
+    bool bucketed = false;
+    if (boba_status e = reorder_run(src, dst, um, un, perm, order, flags & BOBA_FLAG_INTERLEAVED, P, L, flag, stream,
+                                    &bucketed))
+        return e;
+    if (m == 0) return BOBA_OK;
+    if (!bucketed) return relabel_run(src, dst, um, perm, un, src_out, dst_out, flag, stream);
+    BOBA_LAUNCH("bucket_relabel", k_bucket_relabel, dim3(P.nb * P.slices), dim3(kMinThreads), stream,
+                (const uint32_t *)L.recs, (const uint32_t *)L.off_t, P.nt, P.region, P.nb, P.tps, min_batch(P), un,
+                (const int32_t *)perm, L.vals);
+    BOBA_LAUNCH("tile_unsplit", k_tile_unsplit, dim3(P.nt), dim3(kSplitThreads), stream, (const uint32_t *)L.recs,
+                (const uint32_t *)L.vals, (const uint32_t *)L.tile_off, P.nb, P.region, um, P.tiles_half, src_out,
+                dst_out);
+    return BOBA_OK;
+}
+
+extern "C" boba_status boba_relabel(const int32_t *src, const int32_t *dst, int64_t m, const int32_t *perm, int64_t n,
+                                    int32_t *src_out, int32_t *dst_out, hipStream_t stream) {
+    clear_error();
+    if (boba_status e = check_sizes(m, n, false)) return e;
+    if (m == 0) return BOBA_OK;
+    if (!src || !dst || !src_out || !dst_out || !perm)
+        return fail(BOBA_ERR_ARG, "boba_relabel: NULL pointer");
+    if (n == 0) return fail(BOBA_ERR_ARG, "boba_relabel: edges given but n = 0");
+    int32_t *flag = range_flag();
+    if (!flag) return BOBA_ERR_HIP;
+    return relabel_run(src, dst, (uint32_t)m, perm, (uint32_t)n, src_out, dst_out, flag, stream);
 }

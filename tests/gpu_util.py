@@ -47,6 +47,10 @@ def full_path_check(g, boba, interleaved=False, check_spmv=True):
     s2, d2 = boba.boba_relabel(s, d, perm)
     s2_ref, d2_ref = oracle.relabel(g.src, g.dst, p_ref)
     assert np.array_equal(host(s2), s2_ref) and np.array_equal(host(d2), d2_ref), "relabel differs"
+    # fused reorder + relabel gives the same four arrays
+    fp, fo, fs, fd = boba.boba_reorder_relabel(s, d, g.n, flags=flags)
+    assert np.array_equal(host(fp), p_ref) and np.array_equal(host(fo), o_ref), "fused perm/order differ"
+    assert np.array_equal(host(fs), s2_ref) and np.array_equal(host(fd), d2_ref), "fused relabel differs"
     val = dev(g.val) if g.val is not None else None
     rowptr, col, v = boba.coo_to_csr(s2, d2, val, g.n)
     rp_ref, col_ref, v_ref = oracle.coo_to_csr(s2_ref, d2_ref, g.val, g.n)

@@ -232,3 +232,25 @@ def test_spmv_rows_across_chunk_boundaries(lengths):
     assert np.array_equal(y[short], y_ref[short].astype(np.float32))
     # each row individually close
     assert np.all(np.abs(y - y_ref) <= 1e-4 * (1 + np.abs(y_ref)) + 1e-5 * np.sqrt(np.diff(rowptr)))
+
+
+def test_fused_reorder_relabel_in_place_and_unaligned():
+    g = graphgen.small_workload("rmat", 1 << 15, 300001, 86)
+    p_ref, o_ref = oracle.boba(g.src, g.dst, g.n)
+    s_ref, d_ref = oracle.relabel(g.src, g.dst, p_ref)
+    s, d = dev(g.src), dev(g.dst)
+    perm, order, so, do = boba.boba_reorder_relabel(s, d, g.n, src_out=s, dst_out=d)  # in place
+    assert np.array_equal(host(s), s_ref) and np.array_equal(host(d), d_ref)
+    assert np.array_equal(host(perm), p_ref)
+    # unaligned outputs: bucketed reorder, element-wise stores
+    s, d = dev(g.src), dev(g.dst)
+    out_s = torch.empty(g.m + 1, dtype=torch.int32, device="cuda")[1:]
+    out_d = torch.empty(g.m + 1, dtype=torch.int32, device="cuda")[1:]
+    boba.boba_reorder_relabel(s, d, g.n, src_out=out_s, dst_out=out_d)
+    assert np.array_equal(host(out_s), s_ref) and np.array_equal(host(out_d), d_ref)
+    # unaligned inputs: direct path
+    big_s = dev(np.concatenate([[0], g.src]).astype(np.int32))[1:]
+    big_d = dev(np.concatenate([[0], g.dst]).astype(np.int32))[1:]
+    perm, _, so, do = boba.boba_reorder_relabel(big_s, big_d, g.n)
+    assert np.array_equal(host(so), s_ref) and np.array_equal(host(do), d_ref)
+    assert boba.boba_check_device_error() == boba.BOBA_OK
