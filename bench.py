@@ -211,9 +211,12 @@ def main():
         if e:
             e[3].record()
 
-    # x in the new labelling, so the reordered product equals the original one
+    # x in the new labelling (x2[perm[v]] = x[v], on the host), so the
+    # reordered product equals the original one
     boba.boba_reorder(src, dst, n, ws=ws_r, perm=perm, order=order)
-    x2[perm.long()] = x
+    x2_h = np.empty(n, np.float32)
+    x2_h[perm.cpu().numpy()] = g.x
+    x2.copy_(torch.from_numpy(x2_h))
     log(f"warmup {args.warmup} steps")
     for _ in range(args.warmup):
         step()

@@ -89,9 +89,21 @@ def selector_specs(count, seed, log2_lo=10.0, log2_hi=18.0):
     return graphgen.batch_specs(count, seed=seed, log2_lo=log2_lo, log2_hi=log2_hi)
 
 
-def build_dataset(specs, *, reps=5, log=None, workers=0):
+def _gen(spec):
+    return graphgen.make_batch_graph(spec)
+
+
+def start_pool(workers):
+    """A pool of generator processes.  Create it before this process touches
+    the GPU: the workers are forked and never use the GPU themselves."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    return ProcessPoolExecutor(workers, mp_context=mp.get_context("fork"))
+
+
+def build_dataset(specs, *, reps=5, log=None, pool=None):
     """Features (GPU kernel), both path timings and the label for every spec.
-    Graphs are generated in chunks (before each chunk's GPU work)."""
+    Graphs come from `pool` (see start_pool) when given."""
     import torch
 
     from . import boba
@@ -100,29 +112,25 @@ def build_dataset(specs, *, reps=5, log=None, workers=0):
     X = np.zeros((len(specs), N_FEAT), np.float32)
     rows = []
     ws_f = torch.empty(boba.load().boba_graph_features_workspace(), dtype=torch.uint8, device=dev)
-    chunk = 64
-    for c0 in range(0, len(specs), chunk):
-        part = specs[c0:c0 + chunk]
-        graphs = [graphgen.make_batch_graph(s) for s in part]
-        for j, (s, (src_h, dst_h)) in enumerate(zip(part, graphs)):
-            i = c0 + j
-            src = torch.from_numpy(src_h).to(dev)
-            dst = torch.from_numpy(dst_h).to(dev)
-            val = torch.from_numpy(graphgen.uniform_values(src_h.size, s.seed + 3)).to(dev)
-            x = torch.from_numpy(graphgen.uniform_values(s.n, s.seed + 4)).to(dev)
-            # feature + inference overhead as served
-            e = _events(torch, 2)
-            e[0].record()
-            f = boba.boba_graph_features(src, dst, s.n, ws=ws_f)
-            e[1].record()
-            torch.cuda.synchronize()
-            X[i] = f.cpu().numpy()
-            med = measure_paths(src, dst, val, x, s.n, reps=reps)
-            med["t_feat"] = e[0].elapsed_time(e[1])
-            med.update({"kind": s.kind, "n": s.n, "m": int(src_h.size), "seed": s.seed})
-            rows.append(med)
-        if log:
-            log(f"dataset {min(c0 + chunk, len(specs))}/{len(specs)}")
+    graphs = pool.map(_gen, specs, chunksize=4) if pool is not None else map(_gen, specs)
+    for i, (s, (src_h, dst_h)) in enumerate(zip(specs, graphs)):
+        src = torch.from_numpy(src_h).to(dev)
+        dst = torch.from_numpy(dst_h).to(dev)
+        val = torch.from_numpy(graphgen.uniform_values(src_h.size, s.seed + 3)).to(dev)
+        x = torch.from_numpy(graphgen.uniform_values(s.n, s.seed + 4)).to(dev)
+        # feature + inference overhead as served
+        e = _events(torch, 2)
+        e[0].record()
+        f = boba.boba_graph_features(src, dst, s.n, ws=ws_f)
+        e[1].record()
+        torch.cuda.synchronize()
+        X[i] = f.cpu().numpy()
+        med = measure_paths(src, dst, val, x, s.n, reps=reps)
+        med["t_feat"] = e[0].elapsed_time(e[1])
+        med.update({"kind": s.kind, "n": s.n, "m": int(src_h.size), "seed": s.seed})
+        rows.append(med)
+        if log and (i + 1) % 250 == 0:
+            log(f"dataset {i + 1}/{len(specs)}")
     T_never = np.array([r["never"] for r in rows])
     T_always = np.array([r["always"] for r in rows])
     y = np.log2(T_never / T_always).astype(np.float32)
@@ -163,8 +171,9 @@ def train(X, y, *, epochs=200, batch=256, lr=1e-3, seed=0, log=None):
     sigma = X.std(axis=0).astype(np.float64)
     sigma[sigma < 1e-6] = 1.0
     Xs = ((X - mu) / sigma).astype(np.float32)
+    ys = y.astype(np.float32)
     Xd = torch.from_numpy(Xs).to(dev)
-    yd = torch.from_numpy(y.astype(np.float32)).to(dev)
+    yd = torch.from_numpy(ys).to(dev)
     p = torch.from_numpy(init_params(seed)).to(dev)
     m1, m2 = torch.zeros_like(p), torch.zeros_like(p)
     grad = torch.empty_like(p)
@@ -176,9 +185,9 @@ def train(X, y, *, epochs=200, batch=256, lr=1e-3, seed=0, log=None):
     for ep in range(epochs):
         idx = rng.permutation(N)
         for b0 in range(0, N, batch):
-            sel = torch.from_numpy(idx[b0:b0 + batch]).to(dev)
-            xb = Xd.index_select(0, sel).contiguous()
-            yb = yd.index_select(0, sel).contiguous()
+            sel = idx[b0:b0 + batch]  # minibatch rows assembled on the host, then copied
+            xb = torch.from_numpy(np.ascontiguousarray(Xs[sel])).to(dev)
+            yb = torch.from_numpy(np.ascontiguousarray(ys[sel])).to(dev)
             boba.boba_mlp_backward(p, xb, yb, grad=grad, loss=loss)
             step += 1
             boba.boba_mlp_adam(p, m1, m2, grad, step, lr=lr)
@@ -298,15 +307,25 @@ def main(argv=None):
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--epochs", type=int, default=200)
     ap.add_argument("--log2-hi", type=float, default=18.0)
+    ap.add_argument("--large", type=int, default=0, help="extra graphs with log2 n in [log2-hi, large-log2-hi]")
+    ap.add_argument("--large-log2-hi", type=float, default=22.0)
+    ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--out", default="gpurun_out/selector_model.npz")
     ap.add_argument("--data-out", default="gpurun_out/selector_data.npz")
     args = ap.parse_args(argv)
     log = lambda s: print(f"[selector] {s}", file=sys.stderr, flush=True)
     tr_specs = selector_specs(args.train, graphgen.BASE_SEED + 50, log2_hi=args.log2_hi)
     ho_specs = selector_specs(args.heldout, graphgen.BASE_SEED + 51, log2_hi=args.log2_hi)
+    if args.large:
+        k = args.large
+        tr_specs += selector_specs(k, graphgen.BASE_SEED + 52, args.log2_hi, args.large_log2_hi)
+        ho_specs += selector_specs(max(1, k // 8), graphgen.BASE_SEED + 53, args.log2_hi, args.large_log2_hi)
+    pool = start_pool(args.workers) if args.workers > 1 else None  # before the GPU is touched
     t0 = time.perf_counter()
-    Xtr, ytr, rtr = build_dataset(tr_specs, reps=args.reps, log=log)
-    Xho, yho, rho = build_dataset(ho_specs, reps=args.reps, log=log)
+    Xtr, ytr, rtr = build_dataset(tr_specs, reps=args.reps, log=log, pool=pool)
+    Xho, yho, rho = build_dataset(ho_specs, reps=args.reps, log=log, pool=pool)
+    if pool is not None:
+        pool.shutdown()
     log(f"datasets in {time.perf_counter() - t0:.1f}s; train labels: {np.mean(ytr > 0):.3f} reorder-pays")
     params, mu, sigma, hist = train(Xtr, ytr, epochs=args.epochs, log=log)
     os.makedirs(os.path.dirname(args.out) or ".", exist_ok=True)
