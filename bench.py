@@ -134,9 +134,9 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
-        log("multi-GPU runs are not part of this build (one GPU per box); exiting")
+        log("multi-GPU runs are not implemented: the path runs on one GPU; exiting")
         return 2
 
     import numpy as np

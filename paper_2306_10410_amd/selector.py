@@ -310,8 +310,8 @@ def main(argv=None):
     ap.add_argument("--large", type=int, default=0, help="extra graphs with log2 n in [log2-hi, large-log2-hi]")
     ap.add_argument("--large-log2-hi", type=float, default=22.0)
     ap.add_argument("--workers", type=int, default=16)
-    ap.add_argument("--out", default="gpurun_out/selector_model.npz")
-    ap.add_argument("--data-out", default="gpurun_out/selector_data.npz")
+    ap.add_argument("--out", default="selector_model.npz")
+    ap.add_argument("--data-out", default="selector_data.npz")
     args = ap.parse_args(argv)
     log = lambda s: print(f"[selector] {s}", file=sys.stderr, flush=True)
     tr_specs = selector_specs(args.train, graphgen.BASE_SEED + 50, log2_hi=args.log2_hi)
