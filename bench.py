@@ -76,10 +76,16 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
+# library timing name -> device function name, where they differ
+KERNEL_FN = {"bucket_transpose": "k_transpose", "csr_fill": "k_fill_u32", "relabel": "k_relabel_vec",
+             "scatter_min": "k_scatter_min_vec", "spmv": "k_spmv_chunk", "mark": "k_mark_merge"}
+
+
 def pmc_traffic(kernel, workload, launches_per_step):
     """HBM bytes per launch from a committed rocprofv3 PMC summary, if it was
     taken on the current kernel sources; otherwise None."""
-    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}.txt")
+    fn = KERNEL_FN.get(kernel, "k_" + kernel)
+    path = os.path.join(ROOT, "profiles", f"pmc_{fn}_{workload}.txt")
     if not os.path.exists(path):
         return None
     vals = {}
