@@ -50,6 +50,10 @@ def kernel_alg_bytes(name, n, m):
         "tile_unsplit": 24 * m,                # read records and new IDs; write src', dst'
         "rank": 12 * n,                        # read r, write perm, order
         "mark": 4 * n,                         # read r (bitmap writes are ours)
+        "rank_count": 4 * n,                   # read r
+        "rank_scatter": 12 * n,                # read r; write {r, v} per occurring vertex (<= n)
+        "rank_block": 16 * n,                  # read the entries; write ranks and order
+        "rank_perm": 16 * n,                   # read entries and ranks; write perm
     }
     return table.get(name)
 

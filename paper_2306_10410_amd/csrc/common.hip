@@ -54,6 +54,14 @@ int32_t *range_flag() {
     return g_flag_ptr[dev];
 }
 
+uint32_t device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        return 256;
+    return (uint32_t)cus;
+}
+
 }  // namespace boba
 
 extern "C" const char *boba_last_error(void) { return boba::g_msg; }

@@ -17,9 +17,9 @@
 namespace boba {
 namespace {
 
-constexpr int kBlock = 512;
+constexpr int kBlock = 1024;
 constexpr int kNWave = kBlock / kWave;
-constexpr int kItems = 16;
+constexpr int kItems = 8;
 constexpr uint32_t kTile = kBlock * kItems;       // 8192 edges per workgroup: ~128-byte digit runs
 constexpr uint32_t kWaveRun = kWave * kItems;     // contiguous edges per wave
 
@@ -52,8 +52,9 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const int32_t *__restrict
     }
 }
 
+// amdgpu_waves_per_eu(8): at most 64 VGPRs, so that two workgroups share a CU
 template <int BITS, bool HAS_VAL>
-__global__ __launch_bounds__(kBlock) void k_radix_scatter(const int32_t *__restrict__ keys_in,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_radix_scatter(const int32_t *__restrict__ keys_in,
                                                           const int32_t *__restrict__ col_in,
                                                           const float *__restrict__ val_in, uint32_t m,
                                                           uint32_t shift, uint32_t tiles,
@@ -67,32 +68,37 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const int32_t *__restr
     constexpr uint32_t DPT = BINS >= (uint32_t)kBlock ? BINS / kBlock : 1;
     static_assert(BINS % kBlock == 0 || kBlock % BINS == 0, "digit count and block size must divide");
     __shared__ uint32_t s_cnt[kNWave][BINS];  // per-wave counts, then run starts
-    __shared__ uint32_t s_gofs[BINS];
-    __shared__ uint32_t s_start[BINS];
+    __shared__ uint32_t s_gofs[BINS];         // global start of the digit's run minus its tile-local start
     __shared__ uint32_t s_scan[kNWave];
-    __shared__ int32_t s_key[kTile];
-    __shared__ int32_t s_col[kTile];
-    __shared__ float s_val[HAS_VAL ? kTile : 1];
+    // One tile-sized buffer, reused for keys, columns and values in turn, keeps
+    // the LDS footprint near 58 KB: two workgroups per CU overlap one
+    // another's load, rank and store phases.
+    __shared__ int32_t s_buf[kTile];
+    __shared__ uint8_t s_dig[kTile];          // digit of every sorted slot
 
+    const uint32_t tile = xcd_work_index(blockIdx.x, gridDim.x);
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = threadIdx.x / kWave;
     for (uint32_t i = threadIdx.x; i < kNWave * BINS; i += kBlock) (&s_cnt[0][0])[i] = 0;
-    for (uint32_t d = threadIdx.x; d < BINS; d += kBlock) s_gofs[d] = offs[d * tiles + blockIdx.x];
+    for (uint32_t d = threadIdx.x; d < BINS; d += kBlock) s_gofs[d] = offs[d * tiles + tile];
     __syncthreads();
 
-    const uint32_t tile_base = blockIdx.x * kTile;
+    const uint32_t tile_base = tile * kTile;
     const uint32_t wbase = tile_base + wave * kWaveRun;
     const uint64_t lt_mask = (1ull << lane) - 1ull;
+    // Only the keys are held through the ranking; columns and values are
+    // loaded later, each shortly before its own phase (fewer live registers).
     int32_t key[kItems], col[kItems];
     float val[kItems];
-    uint32_t rank[kItems];
+    uint32_t pos[kItems];
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
         const uint32_t i = wbase + j * kWave + lane;
-        const bool valid = i < m;
-        key[j] = valid ? keys_in[i] : 0;
-        col[j] = valid ? col_in[i] : 0;
-        if (HAS_VAL) val[j] = valid ? val_in[i] : 0.f;
+        key[j] = i < m ? keys_in[i] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        const bool valid = wbase + j * kWave + lane < m;
         const uint32_t d = ((uint32_t)key[j] >> shift) & MASK;
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -104,7 +110,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const int32_t *__restr
         const uint32_t below = __popcll(peers & lt_mask);
         const uint32_t prior = s_cnt[wave][d];
         if (valid && below == 0) s_cnt[wave][d] = prior + (uint32_t)__popcll(peers);
-        rank[j] = prior + below;
+        pos[j] = prior + below;  // rank among the wave's equal digits so far
     }
     __syncthreads();
 
@@ -125,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const int32_t *__restr
         for (uint32_t q = 0; q < DPT; ++q) {
             const uint32_t d = threadIdx.x * DPT + q;
             if (!owns) break;
-            s_start[d] = run;
+            s_gofs[d] -= run;  // modulo 2^32; adding back a position in [run, run + count) is exact
 #pragma unroll
             for (int w = 0; w < kNWave; ++w) {
                 const uint32_t c = s_cnt[w][d];
@@ -136,31 +142,65 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const int32_t *__restr
     }
     __syncthreads();
 
-#pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-        const uint32_t i = wbase + j * kWave + lane;
-        if (i < m) {
-            const uint32_t d = ((uint32_t)key[j] >> shift) & MASK;
-            const uint32_t p = s_cnt[wave][d] + rank[j];
-            s_key[p] = key[j];
-            s_col[p] = col[j];
-            if (HAS_VAL) s_val[p] = val[j];
-        }
-    }
-    __syncthreads();
-
     const uint32_t count = m - tile_base < kTile ? m - tile_base : kTile;
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
+        const uint32_t i = wbase + j * kWave + lane;
+        col[j] = i < m ? col_in[i] : 0;
+    }
+    // keys: local sort, then the destination of every sorted slot
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        if (wbase + j * kWave + lane < m) {
+            const uint32_t d = ((uint32_t)key[j] >> shift) & MASK;
+            pos[j] += s_cnt[wave][d];
+            s_buf[pos[j]] = key[j];
+            s_dig[pos[j]] = (uint8_t)d;
+        }
+    }
+    __syncthreads();
+    // destination of sorted slot p (m: none; never the case when the offsets
+    // are consistent)
+    auto dest = [&](uint32_t p) -> uint32_t {
+        if (p >= count) return m;
+        const uint32_t g = s_gofs[s_dig[p]] + p;
+        return g < m ? g : m;
+    };
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
         const uint32_t p = j * kBlock + threadIdx.x;
-        if (p < count) {
-            const int32_t k = s_key[p];
-            const uint32_t d = ((uint32_t)k >> shift) & MASK;
-            const uint32_t g = s_gofs[d] + (p - s_start[d]);
-            if (g >= m) continue;  // unreachable when the offsets are consistent
-            keys_out[g] = k;
-            col_out[g] = s_col[p];
-            if (HAS_VAL) val_out[g] = s_val[p];
+        const uint32_t g = dest(p);
+        if (g < m) keys_out[g] = s_buf[p];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kItems; ++j)
+        if (wbase + j * kWave + lane < m) s_buf[pos[j]] = col[j];
+    if (HAS_VAL) {
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const uint32_t i = wbase + j * kWave + lane;
+            val[j] = i < m ? val_in[i] : 0.f;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        const uint32_t p = j * kBlock + threadIdx.x;
+        const uint32_t g = dest(p);
+        if (g < m) col_out[g] = s_buf[p];
+    }
+    if (HAS_VAL) {
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kItems; ++j)
+            if (wbase + j * kWave + lane < m) s_buf[pos[j]] = __float_as_int(val[j]);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const uint32_t p = j * kBlock + threadIdx.x;
+            const uint32_t g = dest(p);
+            if (g < m) val_out[g] = __int_as_float(s_buf[p]);
         }
     }
 }
@@ -170,18 +210,42 @@ __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *__restrict__ a, u
     for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) a[i] = v;
 }
 
-// rowptr[row + 1] <- end of row's run in the sorted keys.
+// rowptr[row + 1] <- end of row's run in the sorted keys.  Four keys per
+// thread (one int4 load when the keys are 16-byte aligned) plus the next key.
+__device__ __forceinline__ void row_end(int32_t key, int32_t next, uint32_t k, uint32_t m, uint32_t n_rows,
+                                        uint32_t *__restrict__ rowptr, bool &bad) {
+    if ((uint32_t)key >= n_rows) {
+        bad = true;
+        return;
+    }
+    if (k + 1 == m || next != key) rowptr[key + 1] = k + 1;
+}
+
 __global__ __launch_bounds__(kBlock) void k_row_ends(const int32_t *__restrict__ keys, uint32_t m, uint32_t n_rows,
                                                      uint32_t *__restrict__ rowptr, int32_t *flag) {
     const uint32_t stride = gridDim.x * kBlock;
-    for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < m; k += stride) {
-        const int32_t key = keys[k];
-        if ((uint32_t)key >= n_rows) {
-            flag_range_error(flag);
-            continue;
+    const uint32_t groups = (m + 3) / 4;
+    const bool vec = (((uintptr_t)keys) & 15u) == 0;
+    bool bad = false;
+    for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < groups; q += stride) {
+        const uint32_t k = 4 * q;
+        int32_t v[5];
+        if (vec && k + 3 < m) {
+            const v4i x = *(const v4i *)(keys + k);
+            v[0] = x.x;
+            v[1] = x.y;
+            v[2] = x.z;
+            v[3] = x.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = k + j < m ? keys[k + j] : 0;
         }
-        if (k + 1 == m || keys[k + 1] != key) rowptr[key + 1] = k + 1;
+        v[4] = k + 4 < m ? keys[k + 4] : 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (k + j < m) row_end(v[j], v[j + 1], k + j, m, n_rows, rowptr, bad);
     }
+    if (bad) flag_range_error(flag);
 }
 
 constexpr int kBits = 8;
@@ -273,7 +337,7 @@ extern "C" boba_status coo_to_csr(const int32_t *row, const int32_t *col, const 
         cin = cout;
         vin = vout;
     }
-    BOBA_LAUNCH("row_ends", k_row_ends, dim3(grid_for(um, kBlock * 4)), dim3(kBlock), stream, kin, um, nr,
+    BOBA_LAUNCH("row_ends", k_row_ends, dim3(grid_for((um + 3) / 4, kBlock)), dim3(kBlock), stream, kin, um, nr,
                 (uint32_t *)rowptr, flag);
     return device_scan<OpMax, true>("rowptr_scan", LoadArr{(const uint32_t *)rowptr}, StoreArr{(uint32_t *)rowptr}, nr + 1,
                                     L.partial, stream);

@@ -20,6 +20,8 @@ void clear_error();
 // Device address of the per-device "vertex ID out of range" flag (nullptr and
 // an error message on failure).
 int32_t *range_flag();
+// Compute units of the current device (256 on the MI355X; 256 if the query fails).
+uint32_t device_cus();
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 inline uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
@@ -65,6 +67,18 @@ inline uint32_t grid_for(uint64_t items, uint32_t per_block, uint32_t cap = 8192
 }
 
 // ---------------------------------------------------------------- device side
+constexpr uint32_t kXcds = 8;  // MI355X: 8 XCDs, each with its own L2
+
+// Workgroups are handed to the XCDs round-robin by workgroup ID.  This maps
+// workgroup i of a grid of g to a work index such that every XCD gets one
+// contiguous range of work indices, taken in increasing order: neighbouring
+// work items (which share cache lines at their edges) then run on the same
+// XCD at about the same time and meet in its L2.  A bijection on [0, g).
+__device__ __forceinline__ uint32_t xcd_work_index(uint32_t i, uint32_t g) {
+    const uint32_t x = i % kXcds, j = i / kXcds, q = g / kXcds, r = g % kXcds;
+    return x * q + (x < r ? x : r) + j;
+}
+
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 

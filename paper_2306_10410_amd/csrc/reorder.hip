@@ -238,28 +238,16 @@ constexpr int kMinGroup = 16;                                   // segments in f
 
 inline uint32_t split_region(uint32_t nb) { return (kTileT + 3 * nb + 3) & ~3u; }
 
-__global__ __launch_bounds__(kSplitThreads) void k_bucket_split(const int32_t *__restrict__ src,
-                                                                 const int32_t *__restrict__ dst, uint32_t m,
-                                                                 uint32_t tiles_half, uint32_t n, uint32_t nb,
-                                                                 uint32_t region, uint32_t *__restrict__ recs,
-                                                                 uint32_t *__restrict__ tile_off, int32_t *flag) {
-    __shared__ __align__(16) uint32_t stage[kTileT + 3 * kMaxBuckets];
-    __shared__ uint32_t hist[kMaxBuckets];
-    __shared__ uint32_t cur[kMaxBuckets];
-    __shared__ uint32_t scan_lds[kSplitThreads / kWave];
-    const uint32_t tid = threadIdx.x;
-    const uint32_t t = blockIdx.x;
+// Loads tile t (32 elements per thread, element k0 + j*4096 + 4*tid + q, so
+// that every load instruction is coalesced).  Past the end: -1.
+__device__ __forceinline__ void split_load(const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
+                                           uint32_t m, uint32_t tiles_half, uint32_t t, int32_t (&v)[kSplitPer]) {
     const bool h = t >= tiles_half;
     const uint32_t k0 = (t - (h ? tiles_half : 0u)) * kTileT;
     const int32_t *a = h ? dst : src;
-    for (uint32_t i = tid; i < nb; i += kSplitThreads) hist[i] = 0;
-    __syncthreads();
-
-    // element e = k0 + j*4096 + 4*tid + q: every load instruction is coalesced
-    int32_t v[kSplitPer];
 #pragma unroll
     for (int j = 0; j < kSplitPer / 4; ++j) {
-        const uint32_t e = k0 + j * (4 * kSplitThreads) + 4 * tid;
+        const uint32_t e = k0 + j * (4 * kSplitThreads) + 4 * threadIdx.x;
         if (e + 3 < m) {
             const v4i x = __builtin_nontemporal_load((const v4i *)(a + e));
             v[4 * j] = x.x;
@@ -271,55 +259,83 @@ __global__ __launch_bounds__(kSplitThreads) void k_bucket_split(const int32_t *_
             for (int q = 0; q < 4; ++q) v[4 * j + q] = e + q < m ? a[e + q] : -1;
         }
     }
+}
+
+// Persistent: workgroup g takes a contiguous run of tiles.  The next tile's
+// loads are issued right after the current tile has been sorted into LDS, so
+// they are in flight while the current tile's records are written out.
+__global__ __launch_bounds__(kSplitThreads) void k_bucket_split(const int32_t *__restrict__ src,
+                                                                 const int32_t *__restrict__ dst, uint32_t m,
+                                                                 uint32_t tiles_half, uint32_t n, uint32_t nb,
+                                                                 uint32_t region, uint32_t *__restrict__ recs,
+                                                                 uint32_t *__restrict__ tile_off, int32_t *flag) {
+    __shared__ __align__(16) uint32_t stage[kTileT + 3 * kMaxBuckets];
+    __shared__ uint32_t hist[kMaxBuckets];
+    __shared__ uint32_t cur[kMaxBuckets];
+    __shared__ uint32_t scan_lds[kSplitThreads / kWave];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t nt = 2 * tiles_half;
+    const uint32_t per = (nt + gridDim.x - 1) / gridDim.x;
+    const uint32_t t_begin = blockIdx.x * per;
+    const uint32_t t_end = min(nt, t_begin + per);
+    int32_t v[kSplitPer];
+    if (t_begin < t_end) split_load(src, dst, m, tiles_half, t_begin, v);
     bool bad = false;
+    for (uint32_t t = t_begin; t < t_end; ++t) {
+        const bool h = t >= tiles_half;
+        const uint32_t k0 = (t - (h ? tiles_half : 0u)) * kTileT;
+        for (uint32_t i = tid; i < nb; i += kSplitThreads) hist[i] = 0;
+        __syncthreads();
 #pragma unroll
-    for (int j = 0; j < kSplitPer / 4; ++j) {
+        for (int j = 0; j < kSplitPer / 4; ++j) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint32_t e = k0 + j * (4 * kSplitThreads) + 4 * tid + q;
-            const int32_t x = v[4 * j + q];
-            if (e < m) {
-                if ((uint32_t)x < n) {
-                    atomicAdd(&hist[(uint32_t)x >> kVBits], 1u);
-                } else {
-                    bad = true;
-                    v[4 * j + q] = -1;
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t e = k0 + j * (4 * kSplitThreads) + 4 * tid + q;
+                const int32_t x = v[4 * j + q];
+                if (e < m) {
+                    if ((uint32_t)x < n) {
+                        atomicAdd(&hist[(uint32_t)x >> kVBits], 1u);
+                    } else {
+                        bad = true;
+                        v[4 * j + q] = -1;
+                    }
                 }
             }
         }
-    }
-    if (bad) flag_range_error(flag);
-    __syncthreads();
+        __syncthreads();
 
-    const uint32_t c = tid < nb ? hist[tid] : 0u;
-    const uint32_t pc = (c + 3) & ~3u;
-    uint32_t total;
-    const uint32_t start = block_exclusive_scan<kSplitThreads>(pc, OpSum{}, scan_lds, total);
-    uint32_t *off = tile_off + (size_t)t * (nb + 1);
-    if (tid < nb) {
-        off[tid] = start;
-        cur[tid] = start;
-        for (uint32_t q = c; q < pc; ++q) stage[start + q] = kSentinel;
-    }
-    if (tid == 0) off[nb] = total;
-    __syncthreads();
+        const uint32_t c = tid < nb ? hist[tid] : 0u;
+        const uint32_t pc = (c + 3) & ~3u;
+        uint32_t total;
+        const uint32_t start = block_exclusive_scan<kSplitThreads>(pc, OpSum{}, scan_lds, total);
+        uint32_t *off = tile_off + (size_t)t * (nb + 1);
+        if (tid < nb) {
+            off[tid] = start;
+            cur[tid] = start;
+            for (uint32_t q = c; q < pc; ++q) stage[start + q] = kSentinel;
+        }
+        if (tid == 0) off[nb] = total;
+        __syncthreads();
 
 #pragma unroll
-    for (int j = 0; j < kSplitPer / 4; ++j) {
+        for (int j = 0; j < kSplitPer / 4; ++j) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int32_t x = v[4 * j + q];
-            if (x >= 0) {
-                const uint32_t o = j * (4 * kSplitThreads) + 4 * tid + q;
-                const uint32_t slot = atomicAdd(&cur[(uint32_t)x >> kVBits], 1u);
-                stage[slot] = (o << kVBits) | ((uint32_t)x & (kBucketW - 1));
+            for (int q = 0; q < 4; ++q) {
+                const int32_t x = v[4 * j + q];
+                if (x >= 0) {
+                    const uint32_t o = j * (4 * kSplitThreads) + 4 * tid + q;
+                    const uint32_t slot = atomicAdd(&cur[(uint32_t)x >> kVBits], 1u);
+                    stage[slot] = (o << kVBits) | ((uint32_t)x & (kBucketW - 1));
+                }
             }
         }
+        __syncthreads();
+        if (t + 1 < t_end) split_load(src, dst, m, tiles_half, t + 1, v);
+        v4u *out = (v4u *)(recs + (size_t)t * region);
+        const v4u *st = (const v4u *)stage;
+        for (uint32_t i = tid; i < total / 4; i += kSplitThreads) __builtin_nontemporal_store(st[i], &out[i]);
     }
-    __syncthreads();
-    v4u *out = (v4u *)(recs + (size_t)t * region);
-    const v4u *st = (const v4u *)stage;
-    for (uint32_t i = tid; i < total / 4; i += kSplitThreads) __builtin_nontemporal_store(st[i], &out[i]);
+    if (bad) flag_range_error(flag);
 }
 
 // out[c][r] = in[r][c] for an rows x cols matrix of uint32.
@@ -349,8 +365,9 @@ __global__ __launch_bounds__(kMinThreads) void k_bucket_min(const uint32_t *__re
                                                             uint32_t hbase1, uint32_t stride,
                                                             uint32_t *__restrict__ out) {
     __shared__ uint32_t lr[kBucketW];
-    const uint32_t b = blockIdx.x % nb;
-    const uint32_t s = blockIdx.x / nb;
+    const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);  // neighbouring buckets share lines
+    const uint32_t b = w % nb;
+    const uint32_t s = w / nb;
     const uint32_t t0 = s * tps;
     const uint32_t t1 = min(nt, t0 + tps);
     for (uint32_t i = threadIdx.x; i < kBucketW; i += kMinThreads) lr[i] = kInf;
@@ -429,8 +446,9 @@ __global__ __launch_bounds__(kMinThreads) void k_bucket_relabel(const uint32_t *
                                                                 const int32_t *__restrict__ perm,
                                                                 uint32_t *__restrict__ vals) {
     __shared__ uint32_t lp[kBucketW];
-    const uint32_t b = blockIdx.x % nb;
-    const uint32_t s = blockIdx.x / nb;
+    const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);  // neighbouring buckets share lines
+    const uint32_t b = w % nb;
+    const uint32_t s = w / nb;
     const uint32_t t0 = s * tps;
     const uint32_t t1 = min(nt, t0 + tps);
     const uint32_t cntv = min(kBucketW, n - b * kBucketW);
@@ -441,39 +459,46 @@ __global__ __launch_bounds__(kMinThreads) void k_bucket_relabel(const uint32_t *
     constexpr uint32_t NWAVE = kMinThreads / kWave;
     const uint32_t *beg = off_t + (size_t)b * nt;
     const uint32_t *end = off_t + (size_t)(b + 1) * nt;
+    // same batching and software pipelining as bucket_min
     for (uint32_t tb = t0 + wave * batch; tb < t1; tb += NWAVE * batch) {
         const uint32_t cnt = min(batch, t1 - tb);
         const uint32_t sb = lane < cnt ? beg[tb + lane] : 0u;
         const uint32_t se = lane < cnt ? end[tb + lane] : 0u;
-        for (uint32_t g0 = 0; g0 < cnt; g0 += kMinGroup) {
-            uint2 x[kMinGroup];
-            uint32_t kk[kMinGroup];
+        uint2 cur[kMinGroup], nxt[kMinGroup];
+        auto load_group = [&](uint32_t g0, uint2 (&dst)[kMinGroup]) {
 #pragma unroll
             for (int g = 0; g < kMinGroup; ++g) {
                 const uint32_t gi = g0 + g;
                 const uint32_t b0 = __shfl(sb, gi & (kWave - 1), kWave);
                 const uint32_t e0 = __shfl(se, gi & (kWave - 1), kWave);
-                kk[g] = b0 + 2 * lane;
-                x[g] = (gi < cnt && kk[g] < e0) ? *(const uint2 *)(recs + (size_t)(tb + gi) * region + kk[g])
-                                                : make_uint2(kSentinel, kSentinel);
+                const uint32_t k = b0 + 2 * lane;
+                dst[g] = (gi < cnt && k < e0) ? *(const uint2 *)(recs + (size_t)(tb + gi) * region + k)
+                                              : make_uint2(kSentinel, kSentinel);
             }
+        };
+        load_group(0, cur);
+        for (uint32_t g0 = 0; g0 < cnt; g0 += kMinGroup) {
+            if (g0 + kMinGroup < cnt) load_group(g0 + kMinGroup, nxt);
 #pragma unroll
             for (int g = 0; g < kMinGroup; ++g) {
                 const uint32_t gi = g0 + g;
                 const uint32_t tile = tb + gi;
                 const uint32_t e0 = __shfl(se, gi & (kWave - 1), kWave);
-                uint32_t k = kk[g];
-                uint2 r2 = x[g];
+                uint32_t k = __shfl(sb, gi & (kWave - 1), kWave) + 2 * lane;
+                uint2 r2 = cur[g];
+                // segments longer than 128 records (rare) loop here
                 while (gi < cnt && k < e0) {
                     uint2 v;
                     v.x = r2.x != kSentinel ? lp[r2.x & (kBucketW - 1)] : kSentinel;
                     v.y = r2.y != kSentinel ? lp[r2.y & (kBucketW - 1)] : kSentinel;
                     *(uint2 *)(vals + (size_t)tile * region + k) = v;
                     k += 2 * kWave;
-                    if (k >= e0) break;  // segments longer than 128 records (rare)
+                    if (k >= e0) break;
                     r2 = *(const uint2 *)(recs + (size_t)tile * region + k);
                 }
             }
+#pragma unroll
+            for (int g = 0; g < kMinGroup; ++g) cur[g] = nxt[g];
         }
     }
 }
@@ -488,7 +513,7 @@ __global__ __launch_bounds__(kSplitThreads) void k_tile_unsplit(const uint32_t *
     // elements without a record (out-of-range IDs) come out as -1
     for (uint32_t i = threadIdx.x; i < kTileT; i += kSplitThreads) out[i] = kSentinel;
     __syncthreads();
-    const uint32_t t = blockIdx.x;
+    const uint32_t t = xcd_work_index(blockIdx.x, gridDim.x);
     const bool h = t >= tiles_half;
     const uint32_t k0 = (t - (h ? tiles_half : 0u)) * kTileT;
     const uint32_t total = tile_off[(size_t)t * (nb + 1) + nb];
@@ -515,18 +540,158 @@ __global__ __launch_bounds__(kSplitThreads) void k_tile_unsplit(const uint32_t *
     }
 }
 
-// mark with the merge of slice minima: r[v] = min over slices, then set the
-// bitmap bit of key(v).
-__global__ __launch_bounds__(kBlock) void k_mark_merge(uint32_t *__restrict__ rpart, uint32_t slices, uint32_t n,
-                                                       uint32_t tail, uint2 *__restrict__ W) {
-    const uint32_t stride = gridDim.x * kBlock;
-    for (uint32_t v = blockIdx.x * kBlock + threadIdx.x; v < n; v += stride) {
-        uint32_t p = rpart[v];
-        for (uint32_t s = 1; s < slices; ++s) p = min(p, rpart[(size_t)s * n + v]);
-        if (slices > 1) rpart[v] = p;
-        if (p == kInf) p = tail + v;
-        atomicOr(&W[p >> 5].x, 1u << (p & 31));
+// ------------------------------------------- ranking by key blocks (bucketed)
+// After bucket_min, r holds every vertex's first position (kInf when it never
+// occurs).  perm[v] counts the vertices with a smaller key (key = r, or 2m + v
+// in the tail).  Keys below 2m are grouped into key blocks of 2^kbits
+// positions; the isolated vertices form one extra block after them.
+//   rank_count    per vertex bucket: its vertices per key block (LDS counters)
+//   scan          exclusive scan, block-major: where bucket b's entries of key
+//                 block k start in the entry list E (and how many keys precede
+//                 the block)
+//   rank_scatter  per vertex bucket: {r, v} of every occurring vertex into E
+//   rank_block    per key block: its keys as an LDS bitmap with prefix
+//                 popcounts; rank = keys in earlier blocks + keys before it in
+//                 the block; writes order[rank] = v and the rank beside E
+//   rank_perm     per vertex bucket: the ranks back into an LDS perm slice;
+//                 isolated vertices take the tail ranks in increasing ID
+// Every step streams or works in LDS: no device-wide random atomics.
+constexpr uint32_t kMinKeyBits = 15;
+constexpr uint32_t kMaxKeyBits = 19;
+constexpr uint32_t kMaxKeyBlocks = 1u << (32 - kMaxKeyBits);  // 2m < 2^32
+
+__device__ __forceinline__ uint32_t merged_r(const uint32_t *__restrict__ rpart, uint32_t slices, uint32_t n,
+                                             uint32_t v) {
+    uint32_t p = rpart[v];
+    for (uint32_t s = 1; s < slices; ++s) p = min(p, rpart[(size_t)s * n + v]);
+    return p;
+}
+
+__global__ __launch_bounds__(kMinThreads) void k_rank_count(const uint32_t *__restrict__ rpart, uint32_t slices,
+                                                            uint32_t n, uint32_t nb, uint32_t nblk, uint32_t kbits,
+                                                            uint32_t *__restrict__ cnt) {
+    __shared__ uint32_t h[kMaxKeyBlocks + 1];
+    const uint32_t b = blockIdx.x;
+    const uint32_t v0 = b * kBucketW;
+    const uint32_t cntv = min(kBucketW, n - v0);
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    for (uint32_t k = threadIdx.x; k <= nblk; k += kMinThreads) h[k] = 0;
+    if (b == 0 && threadIdx.x == 0) cnt[(size_t)(nblk + 1) * nb] = 0;  // the scan's total lands here
+    __syncthreads();
+    for (uint32_t q = 0; q < kBucketW; q += kMinThreads) {
+        const uint32_t i = q + threadIdx.x;
+        const uint32_t p = i < cntv ? merged_r(rpart, slices, n, v0 + i) : 0u;
+        const bool iso = i < cntv && p == kInf;
+        // isolated vertices are common (about 38% in RMAT): one atomic per wave
+        const uint64_t bal = __ballot(iso);
+        if (iso && lane == (uint32_t)(__ffsll((long long)bal) - 1)) atomicAdd(&h[nblk], (uint32_t)__popcll(bal));
+        if (i < cntv && !iso) atomicAdd(&h[p >> kbits], 1u);
     }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k <= nblk; k += kMinThreads) cnt[(size_t)k * nb + b] = h[k];
+}
+
+__global__ __launch_bounds__(kMinThreads) void k_rank_scatter(const uint32_t *__restrict__ rpart, uint32_t slices,
+                                                              uint32_t n, uint32_t nb, uint32_t nblk, uint32_t kbits,
+                                                              const uint32_t *__restrict__ off, uint2 *__restrict__ E) {
+    __shared__ uint32_t cur[kMaxKeyBlocks];
+    const uint32_t b = blockIdx.x;
+    const uint32_t v0 = b * kBucketW;
+    const uint32_t cntv = min(kBucketW, n - v0);
+    for (uint32_t k = threadIdx.x; k < nblk; k += kMinThreads) cur[k] = off[(size_t)k * nb + b];
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < cntv; i += kMinThreads) {
+        const uint32_t p = merged_r(rpart, slices, n, v0 + i);
+        if (p != kInf) {
+            const uint32_t slot = atomicAdd(&cur[p >> kbits], 1u);
+            E[slot] = make_uint2(p, v0 + i);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kMinThreads) void k_rank_block(const uint2 *__restrict__ E,
+                                                            const uint32_t *__restrict__ off, uint32_t nb,
+                                                            uint32_t kbits, uint32_t *__restrict__ Rk,
+                                                            int32_t *__restrict__ order) {
+    __shared__ uint32_t bits[1u << (kMaxKeyBits - 5)];
+    __shared__ uint16_t pre[1u << (kMaxKeyBits - 5)];   // exclusive popcount within a 64-word group
+    __shared__ uint32_t gbase[1u << (kMaxKeyBits - 11)];  // exclusive popcount of the groups
+    __shared__ uint32_t scan_lds[kMinThreads / kWave];
+    const uint32_t blk = xcd_work_index(blockIdx.x, gridDim.x);
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wave = threadIdx.x / kWave;
+    constexpr uint32_t NWAVE = kMinThreads / kWave;
+    const uint32_t nwords = 1u << (kbits - 5);
+    const uint32_t ngroups = nwords / kWave;
+    for (uint32_t i = threadIdx.x; i < nwords; i += kMinThreads) bits[i] = 0;
+    __syncthreads();
+    const uint32_t e0 = off[(size_t)blk * nb];
+    const uint32_t e1 = off[(size_t)(blk + 1) * nb];
+    const uint32_t base = blk << kbits;
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += kMinThreads) {
+        const uint32_t p = E[e].x - base;
+        atomicOr(&bits[p >> 5], 1u << (p & 31));
+    }
+    __syncthreads();
+    for (uint32_t g = wave; g < ngroups; g += NWAVE) {
+        const uint32_t w = g * kWave + lane;
+        const uint32_t c = __popc(bits[w]);
+        const uint32_t incl = wave_inclusive_scan(c, OpSum{});
+        pre[w] = (uint16_t)(incl - c);
+        if (lane == kWave - 1) gbase[g] = incl;
+    }
+    __syncthreads();
+    uint32_t total;
+    const uint32_t gs = threadIdx.x < ngroups ? gbase[threadIdx.x] : 0u;
+    const uint32_t gex = block_exclusive_scan<kMinThreads>(gs, OpSum{}, scan_lds, total);
+    if (threadIdx.x < ngroups) gbase[threadIdx.x] = gex;
+    __syncthreads();
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += kMinThreads) {
+        const uint2 x = E[e];
+        const uint32_t p = x.x - base;
+        const uint32_t w = p >> 5;
+        const uint32_t k = e0 + gbase[w / kWave] + pre[w] + __popc(bits[w] & ((1u << (p & 31)) - 1u));
+        Rk[e] = k;
+        if (order) order[k] = (int32_t)x.y;
+    }
+}
+
+__global__ __launch_bounds__(kMinThreads) void k_rank_perm(const uint2 *__restrict__ E, const uint32_t *__restrict__ Rk,
+                                                           const uint32_t *__restrict__ off, uint32_t nb,
+                                                           uint32_t nblk, uint32_t n, int32_t *__restrict__ perm,
+                                                           int32_t *__restrict__ order) {
+    __shared__ uint32_t lp[kBucketW];
+    __shared__ uint32_t scan_lds[kMinThreads / kWave];
+    const uint32_t b = blockIdx.x;
+    const uint32_t v0 = b * kBucketW;
+    const uint32_t cntv = min(kBucketW, n - v0);
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wave = threadIdx.x / kWave;
+    constexpr uint32_t NWAVE = kMinThreads / kWave;
+    for (uint32_t i = threadIdx.x; i < kBucketW; i += kMinThreads) lp[i] = kInf;
+    __syncthreads();
+    for (uint32_t blk = wave; blk < nblk; blk += NWAVE) {
+        const uint32_t s0 = off[(size_t)blk * nb + b];
+        const uint32_t s1 = off[(size_t)blk * nb + b + 1];
+        for (uint32_t e = s0 + lane; e < s1; e += kWave) lp[(E[e].y - v0) & (kBucketW - 1)] = Rk[e];
+    }
+    __syncthreads();
+    const uint32_t iso_base = off[(size_t)nblk * nb + b];
+    uint32_t carry = 0;
+    for (uint32_t q = 0; q < kBucketW; q += kMinThreads) {
+        const uint32_t i = q + threadIdx.x;
+        const bool iso = i < cntv && lp[i] == kInf;
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan<kMinThreads>(iso ? 1u : 0u, OpSum{}, scan_lds, tot);
+        if (iso) {
+            const uint32_t k = iso_base + carry + ex;
+            lp[i] = k;
+            if (order) order[k] = (int32_t)(v0 + i);
+        }
+        carry += tot;
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < cntv; i += kMinThreads) perm[v0 + i] = (int32_t)lp[i];
 }
 
 inline bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
@@ -535,6 +700,7 @@ inline bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 struct ReorderPlan {
     bool bucketed;
     uint32_t nb, tiles_half, nt, region, slices, tps;
+    uint32_t kbits, nblk;  // key blocks of the bucketed ranking
 };
 
 ReorderPlan reorder_plan(int64_t n, int64_t m) {
@@ -550,6 +716,11 @@ ReorderPlan reorder_plan(int64_t n, int64_t m) {
         P.slices = s < P.nt ? s : P.nt;
         if (P.slices < 1) P.slices = 1;
         P.region = split_region(P.nb);
+        // about 512 key blocks of 2^15 .. 2^19 positions
+        const uint64_t keys = 2 * (uint64_t)m;
+        P.kbits = kMinKeyBits;
+        while (P.kbits < kMaxKeyBits && (keys >> P.kbits) > 512) ++P.kbits;
+        P.nblk = (uint32_t)((keys + (1ull << P.kbits) - 1) >> P.kbits);
     }
     P.tps = P.nt ? ceil_div(P.nt, P.slices) : 0;
     return P;
@@ -561,6 +732,9 @@ struct ReorderLayout {
     uint32_t *partial;
     uint32_t *recs, *tile_off, *off_t;
     uint32_t *vals;  // new IDs in record layout (fused relabel only)
+    uint32_t *cnt, *cnt_partial, *Rk;  // bucketed ranking
+    uint2 *E;
+    uint32_t ncnt;
     size_t bytes;
     uint32_t nw;
 };
@@ -577,6 +751,11 @@ ReorderLayout reorder_layout(void *ws, int64_t n, int64_t m, const ReorderPlan &
     L.tile_off = c.take<uint32_t>(P.bucketed ? (size_t)P.nt * (P.nb + 1) : 0);
     L.off_t = c.take<uint32_t>(P.bucketed ? (size_t)P.nt * (P.nb + 1) : 0);
     L.vals = c.take<uint32_t>(P.bucketed && with_vals ? (size_t)P.nt * P.region : 0);
+    L.ncnt = P.bucketed ? (P.nblk + 1) * P.nb + 1 : 0;
+    L.cnt = c.take<uint32_t>(L.ncnt);
+    L.cnt_partial = c.take<uint32_t>(P.bucketed ? scan_partials(L.ncnt) : 0);
+    L.E = c.take<uint2>(P.bucketed ? (size_t)n : 0);
+    L.Rk = c.take<uint32_t>(P.bucketed ? (size_t)n : 0);
     L.bytes = c.bytes();
     return L;
 }
@@ -605,17 +784,26 @@ boba_status reorder_run(const int32_t *src, const int32_t *dst, uint32_t um, uin
     *bucketed_out = bucketed;
     const uint32_t tail = 2 * um;
     if (bucketed) {
-        BOBA_LAUNCH("reorder_init", k_reorder_init, dim3(grid_for(L.nw, kBlock * 4)), dim3(kBlock), stream, L.r, 0u,
-                    L.W, L.nw);
-        BOBA_LAUNCH("bucket_split", k_bucket_split, dim3(P.nt), dim3(kSplitThreads), stream, src, dst, um,
+        BOBA_LAUNCH("bucket_split", k_bucket_split, dim3(P.nt < device_cus() ? P.nt : device_cus()),
+                    dim3(kSplitThreads), stream, src, dst, um,
                     P.tiles_half, un, P.nb, P.region, L.recs, L.tile_off, flag);
         BOBA_LAUNCH("bucket_transpose", k_transpose, dim3(ceil_div(P.nb + 1, 32), ceil_div(P.nt, 32)), dim3(256),
                     stream, (const uint32_t *)L.tile_off, P.nt, P.nb + 1, L.off_t);
         BOBA_LAUNCH("bucket_min", k_bucket_min, dim3(P.nb * P.slices), dim3(kMinThreads), stream,
                     (const uint32_t *)L.recs, (const uint32_t *)L.off_t, P.nt, P.tiles_half, P.region, P.nb, P.tps,
                     min_batch(P), un, inter ? 1u : um, inter ? 2u : 1u, L.r);
-        BOBA_LAUNCH("mark", k_mark_merge, dim3(grid_for(un, kBlock * 4)), dim3(kBlock), stream, L.r, P.slices, un,
-                    tail, L.W);
+        BOBA_LAUNCH("rank_count", k_rank_count, dim3(P.nb), dim3(kMinThreads), stream, (const uint32_t *)L.r,
+                    P.slices, un, P.nb, P.nblk, P.kbits, L.cnt);
+        if (boba_status e = device_scan<OpSum, false>("rank_scan", LoadArr{L.cnt}, StoreArr{L.cnt}, L.ncnt,
+                                                      L.cnt_partial, stream))
+            return e;
+        BOBA_LAUNCH("rank_scatter", k_rank_scatter, dim3(P.nb), dim3(kMinThreads), stream, (const uint32_t *)L.r,
+                    P.slices, un, P.nb, P.nblk, P.kbits, (const uint32_t *)L.cnt, L.E);
+        BOBA_LAUNCH("rank_block", k_rank_block, dim3(P.nblk), dim3(kMinThreads), stream, (const uint2 *)L.E,
+                    (const uint32_t *)L.cnt, P.nb, P.kbits, L.Rk, order);
+        BOBA_LAUNCH("rank_perm", k_rank_perm, dim3(P.nb), dim3(kMinThreads), stream, (const uint2 *)L.E,
+                    (const uint32_t *)L.Rk, (const uint32_t *)L.cnt, P.nb, P.nblk, un, perm, order);
+        return BOBA_OK;
     } else {
         BOBA_LAUNCH("reorder_init", k_reorder_init, dim3(grid_for(un > L.nw ? un : L.nw, kBlock * 4)),
                     dim3(kBlock), stream, L.r, un, L.W, L.nw);

@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kThreads) void k_spmv_chunk(const int32_t *__restri
     __shared__ float prod[kChunk];
     __shared__ uint32_t long_rows[kChunk / kShort + 1];
     __shared__ uint32_t n_long;
-    const uint32_t c = blockIdx.x;
+    const uint32_t c = xcd_work_index(blockIdx.x, gridDim.x);  // neighbouring rows share x lines
     const uint32_t e0 = split_j[c];
     const uint32_t e1 = max(e0, min(split_j[c + 1], e0 + kChunk));  // at most kChunk nonzeros
     if (threadIdx.x == 0) {

@@ -254,3 +254,36 @@ def test_fused_reorder_relabel_in_place_and_unaligned():
     perm, _, so, do = boba.boba_reorder_relabel(big_s, big_d, g.n)
     assert np.array_equal(host(so), s_ref) and np.array_equal(host(do), d_ref)
     assert boba.boba_check_device_error() == boba.BOBA_OK
+
+
+# The bucketed ranking groups first positions into key blocks of 2^15 .. 2^19
+# positions (about 512 blocks); these sizes reach every block width, with
+# ragged last blocks and buckets.
+@pytest.mark.parametrize("n,m", [
+    (5000, 7),                      # one key block, one partial bucket
+    (70001, (1 << 17) + 5),         # 2^15-position blocks
+    ((1 << 20) + 3, (1 << 24) + 1), # 2^16
+    ((1 << 21) + 9, (1 << 25) + 3), # 2^17
+    ((1 << 22) + 1, (1 << 26) + 7), # 2^18
+])
+def test_key_block_widths(n, m):
+    src, dst = graphgen.uniform_edges(n, m, 90 + m % 97)
+    perm, order = boba.boba_reorder(dev(src), dev(dst), n)
+    p_ref, o_ref = oracle.boba(src, dst, n)
+    assert np.array_equal(host(perm), p_ref) and np.array_equal(host(order), o_ref)
+    perm, order = boba.boba_reorder(dev(src), dev(dst), n, flags=boba.BOBA_FLAG_INTERLEAVED)
+    p_ref, o_ref = oracle.boba(src, dst, n, interleaved=True)
+    assert np.array_equal(host(perm), p_ref) and np.array_equal(host(order), o_ref)
+
+
+def test_mostly_isolated_and_hub_graphs():
+    # 99.9% isolated vertices (the tail block dominates), then one hub vertex
+    # touching everything (all first positions in the first key block)
+    n = (1 << 21) + 77
+    rng = np.random.default_rng(91)
+    src = rng.integers(0, n, 1000).astype(np.int32)
+    dst = rng.integers(0, n, 1000).astype(np.int32)
+    for s, d in ((src, dst), (np.full(n, 5, np.int32), np.arange(n, dtype=np.int32)[::-1].copy())):
+        perm, order = boba.boba_reorder(dev(s), dev(d), n)
+        p_ref, o_ref = oracle.boba(s, d, n)
+        assert np.array_equal(host(perm), p_ref) and np.array_equal(host(order), o_ref)
