@@ -2,9 +2,9 @@
 // (the conversion step of Sec. 1.1 / Sec. 5.3, moved from the CPU to the GPU).
 //
 // Per digit pass:
-//   hist     per 4096-edge tile, a histogram of the digit (LDS atomics),
-//            stored digit-major: hist[d * tiles + t]
-//   scan     exclusive scan of hist -> where tile t's digit-d run starts
+//   hist     per 8192-edge tile, a histogram of the digit (LDS atomics),
+//            stored tile-major: hist[t * 256 + d]
+//   offsets  column scan of hist -> where tile t's digit-d run starts
 //   scatter  stable rank inside the tile (wave ballots + per-wave LDS
 //            counters, waves own contiguous 1024-edge runs), local sort in
 //            LDS, then coalesced writes of key / col / val runs
@@ -23,32 +23,53 @@ constexpr int kItems = 8;
 constexpr uint32_t kTile = kBlock * kItems;       // 8192 edges per workgroup: ~128-byte digit runs
 constexpr uint32_t kWaveRun = kWave * kItems;     // contiguous edges per wave
 
+// Histogram: 256 threads x 32 keys per tile (int4 loads when aligned), one
+// LDS sub-histogram per wave (skewed digits -- hub rows -- contend less).
+constexpr int kHistThreads = 256;
+constexpr int kHistPer = kTile / kHistThreads;  // 32
+static_assert(kHistPer % 4 == 0, "int4 loads");
+
 template <int BITS>
-__global__ __launch_bounds__(kBlock) void k_radix_hist(const int32_t *__restrict__ keys, uint32_t m, uint32_t shift,
-                                                       uint32_t tiles, uint32_t *__restrict__ hist) {
+__global__ __launch_bounds__(kHistThreads) void k_radix_hist(const int32_t *__restrict__ keys, uint32_t m,
+                                                             uint32_t shift, uint32_t tiles,
+                                                             uint32_t *__restrict__ hist) {
     constexpr uint32_t BINS = 1u << BITS;
-    // one sub-histogram per wave: skewed digits (hub rows) contend less
-    __shared__ uint32_t h[kNWave][BINS];
-    for (uint32_t d = threadIdx.x; d < kNWave * BINS; d += kBlock) (&h[0][0])[d] = 0;
+    constexpr int NW = kHistThreads / kWave;
+    __shared__ uint32_t h[NW][BINS];
+    for (uint32_t d = threadIdx.x; d < NW * BINS; d += kHistThreads) (&h[0][0])[d] = 0;
     __syncthreads();
-    const uint32_t base = blockIdx.x * kTile + threadIdx.x;
     const uint32_t wave = threadIdx.x / kWave;
-    uint32_t k[kItems];
+    const uint32_t base = blockIdx.x * kTile;
+    const bool vec = (((uintptr_t)keys) & 15u) == 0;
+    uint32_t k[kHistPer];
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-        const uint32_t i = base + j * kBlock;
-        k[j] = i < m ? (uint32_t)keys[i] : 0u;
+    for (int j = 0; j < kHistPer / 4; ++j) {
+        const uint32_t e = base + j * (4 * kHistThreads) + 4 * threadIdx.x;
+        if (vec && e + 3 < m) {
+            const v4i x = *(const v4i *)(keys + e);
+            k[4 * j] = (uint32_t)x.x;
+            k[4 * j + 1] = (uint32_t)x.y;
+            k[4 * j + 2] = (uint32_t)x.z;
+            k[4 * j + 3] = (uint32_t)x.w;
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) k[4 * j + q] = e + q < m ? (uint32_t)keys[e + q] : 0u;
+        }
     }
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-        if (base + j * kBlock < m) atomicAdd(&h[wave][(k[j] >> shift) & (BINS - 1)], 1u);
+    for (int j = 0; j < kHistPer / 4; ++j) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (base + j * (4 * kHistThreads) + 4 * threadIdx.x + q < m)
+                atomicAdd(&h[wave][(k[4 * j + q] >> shift) & (BINS - 1)], 1u);
+        }
     }
     __syncthreads();
-    for (uint32_t d = threadIdx.x; d < BINS; d += kBlock) {
+    for (uint32_t d = threadIdx.x; d < BINS; d += kHistThreads) {
         uint32_t t = 0;
 #pragma unroll
-        for (int w = 0; w < kNWave; ++w) t += h[w][d];
-        hist[d * tiles + blockIdx.x] = t;
+        for (int w = 0; w < NW; ++w) t += h[w][d];
+        hist[(size_t)blockIdx.x * BINS + d] = t;  // tile-major: coalesced
     }
 }
 
@@ -80,7 +101,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = threadIdx.x / kWave;
     for (uint32_t i = threadIdx.x; i < kNWave * BINS; i += kBlock) (&s_cnt[0][0])[i] = 0;
-    for (uint32_t d = threadIdx.x; d < BINS; d += kBlock) s_gofs[d] = offs[d * tiles + tile];
+    for (uint32_t d = threadIdx.x; d < BINS; d += kBlock) s_gofs[d] = offs[(size_t)tile * BINS + d];
     __syncthreads();
 
     const uint32_t tile_base = tile * kTile;
@@ -205,6 +226,49 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     }
 }
 
+// Offsets from the tile-major histograms: offs[t][d] = start of digit d's
+// bucket + count of digit d in tiles before t.  Per block of kColTiles tiles
+// the column sums are written digit-major (partial[d * blocks + b]); a plain
+// exclusive scan of that array gives every (digit, block) its start; then each
+// block's running sums are written in place.  Rows of the histogram are read
+// coalesced, one thread per digit, kColUnroll rows in flight.
+constexpr uint32_t kColTiles = 64;
+constexpr int kColUnroll = 16;
+
+template <int BINS>
+__global__ __launch_bounds__(BINS) void k_col_reduce(const uint32_t *__restrict__ hist, uint32_t tiles,
+                                                     uint32_t blocks, uint32_t *__restrict__ partial) {
+    const uint32_t b = blockIdx.x, d = threadIdx.x;
+    const uint32_t t0 = b * kColTiles, t1 = min(tiles, t0 + kColTiles);
+    uint32_t s = 0;
+    for (uint32_t t = t0; t < t1; t += kColUnroll) {
+        uint32_t v[kColUnroll];
+#pragma unroll
+        for (int u = 0; u < kColUnroll; ++u) v[u] = t + u < t1 ? hist[(size_t)(t + u) * BINS + d] : 0u;
+#pragma unroll
+        for (int u = 0; u < kColUnroll; ++u) s += v[u];
+    }
+    partial[(size_t)d * blocks + b] = s;
+}
+
+template <int BINS>
+__global__ __launch_bounds__(BINS) void k_col_down(uint32_t *__restrict__ hist, uint32_t tiles, uint32_t blocks,
+                                                   const uint32_t *__restrict__ partial) {
+    const uint32_t b = blockIdx.x, d = threadIdx.x;
+    const uint32_t t0 = b * kColTiles, t1 = min(tiles, t0 + kColTiles);
+    uint32_t run = partial[(size_t)d * blocks + b];
+    for (uint32_t t = t0; t < t1; t += kColUnroll) {
+        uint32_t v[kColUnroll];
+#pragma unroll
+        for (int u = 0; u < kColUnroll; ++u) v[u] = t + u < t1 ? hist[(size_t)(t + u) * BINS + d] : 0u;
+#pragma unroll
+        for (int u = 0; u < kColUnroll; ++u) {
+            if (t + u < t1) hist[(size_t)(t + u) * BINS + d] = run;
+            run += v[u];
+        }
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *__restrict__ a, uint32_t count, uint32_t v) {
     const uint32_t stride = gridDim.x * kBlock;
     for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) a[i] = v;
@@ -253,9 +317,9 @@ constexpr int kBits = 8;
 struct CsrLayout {
     int32_t *keys_a, *keys_b, *col_x;
     float *val_x;
-    uint32_t *hist, *partial;
+    uint32_t *hist, *partial, *colpart;
     size_t bytes;
-    uint32_t tiles;
+    uint32_t tiles, colblocks;
 };
 
 CsrLayout csr_layout(void *ws, int64_t n_rows, int64_t m, bool has_val) {
@@ -270,6 +334,8 @@ CsrLayout csr_layout(void *ws, int64_t n_rows, int64_t m, bool has_val) {
     L.val_x = c.take<float>(has_val ? (size_t)m : 0);
     L.hist = c.take<uint32_t>((size_t)hist_count);
     L.partial = c.take<uint32_t>(scan_partials(scan_count));
+    L.colblocks = ceil_div(L.tiles, kColTiles);
+    L.colpart = c.take<uint32_t>((size_t)L.colblocks << kBits);
     L.bytes = c.bytes();
     return L;
 }
@@ -312,7 +378,6 @@ extern "C" boba_status coo_to_csr(const int32_t *row, const int32_t *col, const 
     uint32_t bits = 0;
     while (bits < 31 && (1ull << bits) < (uint64_t)nr) ++bits;
     const int passes = bits == 0 ? 1 : (int)((bits + kBits - 1) / kBits);
-    const uint32_t hist_count = (1u << kBits) * L.tiles;
 
     const int32_t *kin = row;
     const int32_t *cin = col;
@@ -323,10 +388,15 @@ extern "C" boba_status coo_to_csr(const int32_t *row, const int32_t *col, const 
         int32_t *kout = (p % 2 == 0) ? L.keys_a : L.keys_b;
         int32_t *cout = to_out ? col_out : L.col_x;
         float *vout = to_out ? val_out : L.val_x;
-        BOBA_LAUNCH("radix_hist", k_radix_hist<kBits>, dim3(L.tiles), dim3(kBlock), stream, kin, um, shift, L.tiles,
+        BOBA_LAUNCH("radix_hist", k_radix_hist<kBits>, dim3(L.tiles), dim3(kHistThreads), stream, kin, um, shift, L.tiles,
                     L.hist);
-        if (boba_status e = device_scan<OpSum, false>("radix_offsets", LoadArr{L.hist}, StoreArr{L.hist}, hist_count, L.partial, stream))
+        BOBA_LAUNCH("radix_offsets", k_col_reduce<1 << kBits>, dim3(L.colblocks), dim3(1 << kBits), stream,
+                    (const uint32_t *)L.hist, L.tiles, L.colblocks, L.colpart);
+        if (boba_status e = device_scan<OpSum, false>("radix_offsets", LoadArr{L.colpart}, StoreArr{L.colpart},
+                                                      L.colblocks << kBits, L.partial, stream))
             return e;
+        BOBA_LAUNCH("radix_offsets", k_col_down<1 << kBits>, dim3(L.colblocks), dim3(1 << kBits), stream, L.hist,
+                    L.tiles, L.colblocks, (const uint32_t *)L.colpart);
         if (has_val)
             BOBA_LAUNCH("radix_scatter", (k_radix_scatter<kBits, true>), dim3(L.tiles), dim3(kBlock), stream, kin, cin,
                         vin, um, shift, L.tiles, (const uint32_t *)L.hist, kout, cout, vout);

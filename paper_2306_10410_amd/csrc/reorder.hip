@@ -365,9 +365,8 @@ __global__ __launch_bounds__(kMinThreads) void k_bucket_min(const uint32_t *__re
                                                             uint32_t hbase1, uint32_t stride,
                                                             uint32_t *__restrict__ out) {
     __shared__ uint32_t lr[kBucketW];
-    const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);  // neighbouring buckets share lines
-    const uint32_t b = w % nb;
-    const uint32_t s = w / nb;
+    const uint32_t b = blockIdx.x % nb;
+    const uint32_t s = blockIdx.x / nb;
     const uint32_t t0 = s * tps;
     const uint32_t t1 = min(nt, t0 + tps);
     for (uint32_t i = threadIdx.x; i < kBucketW; i += kMinThreads) lr[i] = kInf;
@@ -544,7 +543,8 @@ __global__ __launch_bounds__(kSplitThreads) void k_tile_unsplit(const uint32_t *
 // After bucket_min, r holds every vertex's first position (kInf when it never
 // occurs).  perm[v] counts the vertices with a smaller key (key = r, or 2m + v
 // in the tail).  Keys below 2m are grouped into key blocks of 2^kbits
-// positions; the isolated vertices form one extra block after them.
+// positions (about 4096 blocks); the isolated vertices form one extra block
+// after them.
 //   rank_count    per vertex bucket: its vertices per key block (LDS counters)
 //   scan          exclusive scan, block-major: where bucket b's entries of key
 //                 block k start in the entry list E (and how many keys precede
@@ -558,7 +558,8 @@ __global__ __launch_bounds__(kSplitThreads) void k_tile_unsplit(const uint32_t *
 // Every step streams or works in LDS: no device-wide random atomics.
 constexpr uint32_t kMinKeyBits = 15;
 constexpr uint32_t kMaxKeyBits = 19;
-constexpr uint32_t kMaxKeyBlocks = 1u << (32 - kMaxKeyBits);  // 2m < 2^32
+constexpr uint32_t kTargetKeyBlocks = 4096;                    // bounds a key block's entries
+constexpr uint32_t kMaxKeyBlocks = 2 * kTargetKeyBlocks;       // 2m < 2^32 at 2^19 positions per block
 
 __device__ __forceinline__ uint32_t merged_r(const uint32_t *__restrict__ rpart, uint32_t slices, uint32_t n,
                                              uint32_t v) {
@@ -600,11 +601,20 @@ __global__ __launch_bounds__(kMinThreads) void k_rank_scatter(const uint32_t *__
     const uint32_t cntv = min(kBucketW, n - v0);
     for (uint32_t k = threadIdx.x; k < nblk; k += kMinThreads) cur[k] = off[(size_t)k * nb + b];
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < cntv; i += kMinThreads) {
-        const uint32_t p = merged_r(rpart, slices, n, v0 + i);
-        if (p != kInf) {
-            const uint32_t slot = atomicAdd(&cur[p >> kbits], 1u);
-            E[slot] = make_uint2(p, v0 + i);
+    constexpr int U = 8;
+    for (uint32_t i0 = threadIdx.x; i0 < cntv; i0 += U * kMinThreads) {
+        uint32_t p[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t i = i0 + u * kMinThreads;
+            p[u] = i < cntv ? merged_r(rpart, slices, n, v0 + i) : kInf;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (p[u] != kInf) {
+                const uint32_t slot = atomicAdd(&cur[p[u] >> kbits], 1u);
+                E[slot] = make_uint2(p[u], v0 + i0 + u * kMinThreads);
+            }
         }
     }
 }
@@ -628,9 +638,17 @@ __global__ __launch_bounds__(kMinThreads) void k_rank_block(const uint2 *__restr
     const uint32_t e0 = off[(size_t)blk * nb];
     const uint32_t e1 = off[(size_t)(blk + 1) * nb];
     const uint32_t base = blk << kbits;
-    for (uint32_t e = e0 + threadIdx.x; e < e1; e += kMinThreads) {
-        const uint32_t p = E[e].x - base;
-        atomicOr(&bits[p >> 5], 1u << (p & 31));
+    constexpr int U = 8;  // entries in flight per thread
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += U * kMinThreads) {
+        uint32_t p[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t i = e + u * kMinThreads;
+            p[u] = i < e1 ? E[i].x - base : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (e + u * kMinThreads < e1) atomicOr(&bits[p[u] >> 5], 1u << (p[u] & 31));
     }
     __syncthreads();
     for (uint32_t g = wave; g < ngroups; g += NWAVE) {
@@ -646,13 +664,23 @@ __global__ __launch_bounds__(kMinThreads) void k_rank_block(const uint2 *__restr
     const uint32_t gex = block_exclusive_scan<kMinThreads>(gs, OpSum{}, scan_lds, total);
     if (threadIdx.x < ngroups) gbase[threadIdx.x] = gex;
     __syncthreads();
-    for (uint32_t e = e0 + threadIdx.x; e < e1; e += kMinThreads) {
-        const uint2 x = E[e];
-        const uint32_t p = x.x - base;
-        const uint32_t w = p >> 5;
-        const uint32_t k = e0 + gbase[w / kWave] + pre[w] + __popc(bits[w] & ((1u << (p & 31)) - 1u));
-        Rk[e] = k;
-        if (order) order[k] = (int32_t)x.y;
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += U * kMinThreads) {
+        uint2 x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t i = e + u * kMinThreads;
+            x[u] = i < e1 ? E[i] : make_uint2(base, 0u);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t i = e + u * kMinThreads;
+            if (i >= e1) continue;
+            const uint32_t p = x[u].x - base;
+            const uint32_t w = p >> 5;
+            const uint32_t k = e0 + gbase[w / kWave] + pre[w] + __popc(bits[w] & ((1u << (p & 31)) - 1u));
+            Rk[i] = k;
+            if (order) order[k] = (int32_t)x[u].y;
+        }
     }
 }
 
@@ -670,10 +698,36 @@ __global__ __launch_bounds__(kMinThreads) void k_rank_perm(const uint2 *__restri
     constexpr uint32_t NWAVE = kMinThreads / kWave;
     for (uint32_t i = threadIdx.x; i < kBucketW; i += kMinThreads) lp[i] = kInf;
     __syncthreads();
-    for (uint32_t blk = wave; blk < nblk; blk += NWAVE) {
-        const uint32_t s0 = off[(size_t)blk * nb + b];
-        const uint32_t s1 = off[(size_t)blk * nb + b + 1];
-        for (uint32_t e = s0 + lane; e < s1; e += kWave) lp[(E[e].y - v0) & (kBucketW - 1)] = Rk[e];
+    // wave w takes key blocks [64 w', 64 w' + 64) for w' = w, w + 16, ...: one
+    // coalesced-ish load of 64 segment bounds, then the first 64 entries of 8
+    // segments at a time; longer segments finish in a loop
+    constexpr int U = 8;
+    for (uint32_t g = wave * kWave; g < nblk; g += NWAVE * kWave) {
+        const uint32_t my = g + lane;
+        const uint32_t sb = my < nblk ? off[(size_t)my * nb + b] : 0u;
+        const uint32_t se = my < nblk ? off[(size_t)my * nb + b + 1] : 0u;
+        const uint32_t cnt = min((uint32_t)kWave, nblk - g);
+        for (uint32_t j0 = 0; j0 < cnt; j0 += U) {
+            uint32_t vv[U], rk[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t j = j0 + u;
+                const uint32_t b0 = __shfl(sb, j & (kWave - 1), kWave);
+                const uint32_t e0 = __shfl(se, j & (kWave - 1), kWave);
+                const uint32_t e = b0 + lane;
+                const bool ok = j < cnt && e < e0;
+                vv[u] = ok ? E[e].y : kInf;
+                rk[u] = ok ? Rk[e] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (vv[u] != kInf) lp[(vv[u] - v0) & (kBucketW - 1)] = rk[u];
+        }
+        for (uint32_t j = 0; j < cnt; ++j) {  // entries beyond the first 64 (dense key blocks)
+            const uint32_t b0 = __shfl(sb, j, kWave);
+            const uint32_t e0 = __shfl(se, j, kWave);
+            for (uint32_t e = b0 + kWave + lane; e < e0; e += kWave) lp[(E[e].y - v0) & (kBucketW - 1)] = Rk[e];
+        }
     }
     __syncthreads();
     const uint32_t iso_base = off[(size_t)nblk * nb + b];
@@ -716,10 +770,12 @@ ReorderPlan reorder_plan(int64_t n, int64_t m) {
         P.slices = s < P.nt ? s : P.nt;
         if (P.slices < 1) P.slices = 1;
         P.region = split_region(P.nb);
-        // about 512 key blocks of 2^15 .. 2^19 positions
+        // about 4096 key blocks of 2^15 .. 2^19 positions: the first blocks of
+        // a graph hold most first occurrences, and a small block bounds the
+        // work of the workgroup that ranks it
         const uint64_t keys = 2 * (uint64_t)m;
         P.kbits = kMinKeyBits;
-        while (P.kbits < kMaxKeyBits && (keys >> P.kbits) > 512) ++P.kbits;
+        while (P.kbits < kMaxKeyBits && (keys >> P.kbits) > kTargetKeyBlocks) ++P.kbits;
         P.nblk = (uint32_t)((keys + (1ull << P.kbits) - 1) >> P.kbits);
     }
     P.tps = P.nt ? ceil_div(P.nt, P.slices) : 0;

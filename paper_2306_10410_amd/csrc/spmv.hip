@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kThreads) void k_spmv_chunk(const int32_t *__restri
     __shared__ float prod[kChunk];
     __shared__ uint32_t long_rows[kChunk / kShort + 1];
     __shared__ uint32_t n_long;
-    const uint32_t c = xcd_work_index(blockIdx.x, gridDim.x);  // neighbouring rows share x lines
+    const uint32_t c = blockIdx.x;
     const uint32_t e0 = split_j[c];
     const uint32_t e1 = max(e0, min(split_j[c + 1], e0 + kChunk));  // at most kChunk nonzeros
     if (threadIdx.x == 0) {
@@ -84,21 +84,31 @@ __global__ __launch_bounds__(kThreads) void k_spmv_chunk(const int32_t *__restri
         tail_row[c] = kNoRow;
     }
 
+    // Branch-free: every load of a thread is issued before the first use (out
+    // of range entries read a clamped, valid address and are masked after).
     bool bad = false;
+    if (e1 > e0) {  // uniform; a chunk of row ends only has no nonzero to read
+        int32_t cc[kItems];
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-        const uint32_t i = j * kThreads + threadIdx.x;
-        const uint32_t e = e0 + i;
-        float p = 0.f;
-        if (e < e1) {
-            const int32_t cc = col[e];
-            if ((uint32_t)cc < n_cols) {
-                p = HAS_VAL ? val[e] * x[cc] : x[cc];
-            } else {
-                bad = true;
-            }
+        for (int j = 0; j < kItems; ++j) {
+            const uint32_t e = e0 + j * kThreads + threadIdx.x;
+            cc[j] = col[e < e1 ? e : e0];
         }
-        prod[i] = p;
+        float xv[kItems], vv[kItems];
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const uint32_t e = e0 + j * kThreads + threadIdx.x;
+            xv[j] = x[(uint32_t)cc[j] < n_cols ? (uint32_t)cc[j] : 0u];
+            vv[j] = HAS_VAL ? val[e < e1 ? e : e0] : 1.f;
+        }
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const uint32_t i = j * kThreads + threadIdx.x;
+            const bool live = e0 + i < e1;
+            const bool ok = (uint32_t)cc[j] < n_cols;
+            bad |= live && !ok;
+            prod[i] = live && ok ? (HAS_VAL ? vv[j] * xv[j] : xv[j]) : 0.f;
+        }
     }
     if (bad) flag_range_error(flag);
     __syncthreads();

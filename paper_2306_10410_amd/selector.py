@@ -13,7 +13,7 @@ reordering (the method itself).
 
 Labels are measured by the method itself on the GPU:
     T_never  = t(coo_to_csr on input labels) + spmv_iters * t(spmv on it)
-    T_always = t(boba_reorder) + t(boba_relabel) + t(coo_to_csr on BOBA labels)
+    T_always = t(boba_reorder_relabel) + t(coo_to_csr on BOBA labels)
                + spmv_iters * t(spmv on it)
 each the median of `reps` HIP-event timings.  Training uses the library's own
 backward and Adam kernels.
@@ -55,31 +55,29 @@ def measure_paths(src, dst, val, x, n, *, reps=5, spmv_iters=SPMV_ITERS, ws=None
     s2, d2 = torch.empty_like(src), torch.empty_like(dst)
     perm = torch.empty(n, dtype=torch.int32, device=dev)
     order = torch.empty(n, dtype=torch.int32, device=dev)
-    ws_r = torch.empty(max(1, boba.boba_reorder_workspace(n, m)), dtype=torch.uint8, device=dev)
+    ws_r = torch.empty(max(1, boba.boba_reorder_relabel_workspace(n, m)), dtype=torch.uint8, device=dev)
     ws_c = torch.empty(max(1, boba.coo_to_csr_workspace(n, m)), dtype=torch.uint8, device=dev)
     ws_s = torch.empty(max(1, boba.spmv_csr_workspace(n, m)), dtype=torch.uint8, device=dev)
-    t = {k: [] for k in ("csr_in", "spmv_in", "reorder", "relabel", "csr_boba", "spmv_boba")}
+    t = {k: [] for k in ("csr_in", "spmv_in", "reorder_relabel", "csr_boba", "spmv_boba")}
     for _ in range(reps + 1):  # first round warms up
-        e = _events(torch, 8)
+        e = _events(torch, 6)
         e[0].record()
         boba.coo_to_csr(src, dst, val, n, ws=ws_c, out=(rp, col, vv))
         e[1].record()
         boba.spmv_csr(rp, col, vv, x, y=y, ws=ws_s)
         e[2].record()
-        boba.boba_reorder(src, dst, n, ws=ws_r, perm=perm, order=order)
+        boba.boba_reorder_relabel(src, dst, n, ws=ws_r, perm=perm, order=order, src_out=s2, dst_out=d2)
         e[3].record()
-        boba.boba_relabel(src, dst, perm, src_out=s2, dst_out=d2)
-        e[4].record()
         boba.coo_to_csr(s2, d2, val, n, ws=ws_c, out=(rp, col, vv))
-        e[5].record()
+        e[4].record()
         boba.spmv_csr(rp, col, vv, x, y=y, ws=ws_s)  # x in any labelling: same access pattern cost
-        e[6].record()
+        e[5].record()
         torch.cuda.synchronize()
         for i, k in enumerate(t):
             t[k].append(e[i].elapsed_time(e[i + 1]))
     med = {k: float(np.median(v[1:])) for k, v in t.items()}
     med["never"] = med["csr_in"] + spmv_iters * med["spmv_in"]
-    med["always"] = med["reorder"] + med["relabel"] + med["csr_boba"] + spmv_iters * med["spmv_boba"]
+    med["always"] = med["reorder_relabel"] + med["csr_boba"] + spmv_iters * med["spmv_boba"]
     return med
 
 

@@ -257,14 +257,15 @@ def test_fused_reorder_relabel_in_place_and_unaligned():
 
 
 # The bucketed ranking groups first positions into key blocks of 2^15 .. 2^19
-# positions (about 512 blocks); these sizes reach every block width, with
-# ragged last blocks and buckets.
+# positions (about 4096 blocks); these sizes give one block, a few, 1025, 4097
+# (2^15 positions each) and 2051 (2^16), with ragged last blocks and buckets.
+# RMAT-24 (2^17-position blocks) is in the full-scale tests.
 @pytest.mark.parametrize("n,m", [
-    (5000, 7),                      # one key block, one partial bucket
-    (70001, (1 << 17) + 5),         # 2^15-position blocks
-    ((1 << 20) + 3, (1 << 24) + 1), # 2^16
-    ((1 << 21) + 9, (1 << 25) + 3), # 2^17
-    ((1 << 22) + 1, (1 << 26) + 7), # 2^18
+    (5000, 7),
+    (70001, (1 << 17) + 5),
+    ((1 << 20) + 3, (1 << 24) + 1),
+    ((1 << 21) + 9, (1 << 26) + 7),
+    ((1 << 22) + 1, (1 << 26) + (1 << 16) + 7),
 ])
 def test_key_block_widths(n, m):
     src, dst = graphgen.uniform_edges(n, m, 90 + m % 97)
