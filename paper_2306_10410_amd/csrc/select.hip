@@ -10,8 +10,9 @@
 //   10,11 mean over windows of #distinct (id >> 5) / L   (src, dst)
 //   12,13 mean over windows of #(id_e == id_{e-1}) / (L-1)
 //   14,15 mean over windows of #(|id_e - id_{e-1}| < 32) / (L-1)
-// Counts are exact integers; the final combination is done in FP64 in a fixed
-// order and rounded to FP32.  No value is used as an index, so any input is safe.
+// Counts are exact integers (equal samples and distinct lines are counted in
+// LDS hash tables); the final combination is done in FP64 in a fixed order and
+// rounded to FP32.  No value is used as an index, so any input is safe.
 //
 // MLP parameters, row-major, FP32: W1[64][16] b1[64] W2[64][64] b2[64] W3[1][64] b3[1].
 // Forward: one thread per sample, weights staged in LDS.  Backward: per-sample
@@ -33,27 +34,6 @@ constexpr int kT = 1024;  // threads of the feature kernels
 constexpr int kWinStats = 7;    // absdiff, lines src, lines dst, eq src, eq dst, near src, near dst
 constexpr int kSpreadStats = 3; // collisions, max count, distinct
 constexpr size_t kFeatWsWords = (size_t)kWin * kWinStats + 2 * kSpreadStats;
-
-// Ascending bitonic sort of N (power of two) uint32 in LDS by kT threads.
-template <int N>
-__device__ void bitonic(uint32_t *a) {
-    for (int k = 2; k <= N; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < N; i += kT) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const uint32_t x = a[i], y = a[l];
-                    const bool up = (i & k) == 0;
-                    if ((x > y) == up) {
-                        a[i] = y;
-                        a[l] = x;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-}
 
 __device__ uint64_t block_sum64(uint64_t x, uint64_t *lds) {
     for (int d = kWave / 2; d >= 1; d >>= 1) x += __shfl_xor(x, d, kWave);
@@ -77,78 +57,99 @@ __device__ uint32_t block_max32(uint32_t x, uint32_t *lds) {
     return t;
 }
 
-// One workgroup per window.
-__global__ __launch_bounds__(kT) void k_feat_windows(const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
-                                                     uint32_t m, uint64_t *__restrict__ out) {
-    __shared__ uint32_t a[kWinLen];
-    __shared__ uint64_t red[kT / kWave];
-    const uint32_t L = min((uint32_t)kWinLen, m);
-    const uint32_t s0 = (uint32_t)(((uint64_t)blockIdx.x * (m - L)) / (kWin - 1));
-    const uint32_t t = threadIdx.x;
-    const bool live = t < L;
-    const int32_t vs = live ? src[s0 + t] : 0, vd = live ? dst[s0 + t] : 0;
-    const int32_t ps = live && t > 0 ? src[s0 + t - 1] : 0, pd = live && t > 0 ? dst[s0 + t - 1] : 0;
-    uint64_t st[kWinStats];
-    st[0] = live ? (uint64_t)llabs((long long)vs - (long long)vd) : 0;
-    const bool pair = live && t > 0;
-    st[3] = pair && vs == ps;
-    st[4] = pair && vd == pd;
-    st[5] = pair && llabs((long long)vs - (long long)ps) < 32;
-    st[6] = pair && llabs((long long)vd - (long long)pd) < 32;
-    // distinct cache lines (id >> 5): sort, count run starts (padding sorts last)
-    for (int side = 0; side < 2; ++side) {
-        const int32_t v = side == 0 ? vs : vd;
-        a[t] = live ? ((uint32_t)v >> 5) : 0xFFFFFFFFu;
-        __syncthreads();
-        bitonic<kWinLen>(a);
-        st[1 + side] = live && (t == 0 || a[t] != a[t - 1]);
-        __syncthreads();
-    }
-    uint64_t *o = out + (size_t)blockIdx.x * kWinStats;
-    for (int q = 0; q < kWinStats; ++q) {
-        const uint64_t tot = block_sum64(st[q], red);
-        if (t == 0) o[q] = tot;
-    }
-}
+// Exact counting with open-addressing hash tables in LDS (linear probing; a
+// table has at least twice as many slots as keys, so every insert ends).
+__device__ __forceinline__ uint32_t fib_hash(uint32_t k, int bits) { return (k * 0x9E3779B1u) >> (32 - bits); }
 
-// Workgroup 0: sources, 1: destinations.
-__global__ __launch_bounds__(kT) void k_feat_spread(const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
-                                                    uint32_t m, uint64_t *__restrict__ out) {
-    __shared__ uint32_t a[kSpread];
+constexpr int kSpreadBits = 13;  // 8192 slots for 4096 samples
+constexpr int kWinBits = 11;     // 2048 slots for <= 1024 keys
+constexpr uint32_t kEmpty32 = 0xFFFFFFFFu;
+constexpr unsigned long long kEmpty64 = ~0ull;
+
+// Workgroups 0 .. kWin-1: windows; kWin, kWin+1: spread samples of src, dst.
+// One launch; every workgroup writes its own counters.
+__global__ __launch_bounds__(kT) void k_feat_stats(const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
+                                                   uint32_t m, uint64_t *__restrict__ out) {
+    __shared__ unsigned long long key[1 << kSpreadBits];  // spread keys; windows use the first words as uint32
+    __shared__ uint32_t cnt[1 << kSpreadBits];
     __shared__ uint64_t red[kT / kWave];
     __shared__ uint32_t red32[kT / kWave];
-    const int32_t *arr = blockIdx.x == 0 ? src : dst;
-    for (int k = threadIdx.x; k < kSpread; k += kT) a[k] = (uint32_t)arr[((uint64_t)k * m) / kSpread];
-    __syncthreads();
-    bitonic<kSpread>(a);
-    // start[i] = index where the run holding i begins: inclusive max-scan of run heads
-    constexpr int PER = kSpread / kT;
-    uint32_t loc[PER];
-    uint32_t run = 0;
-    for (int q = 0; q < PER; ++q) {
-        const int i = threadIdx.x * PER + q;
-        const uint32_t head = (i == 0 || a[i] != a[i - 1]) ? (uint32_t)i : 0u;
-        run = max(run, head);
-        loc[q] = run;
+    const uint32_t t = threadIdx.x;
+    if (blockIdx.x < kWin) {
+        uint32_t *tab = (uint32_t *)key;  // two tables of 2^kWinBits words
+        for (uint32_t i = t; i < (2u << kWinBits); i += kT) tab[i] = kEmpty32;
+        const uint32_t L = min((uint32_t)kWinLen, m);
+        const uint32_t s0 = (uint32_t)(((uint64_t)blockIdx.x * (m - L)) / (kWin - 1));
+        const bool live = t < L;
+        const int32_t vs = live ? src[s0 + t] : 0, vd = live ? dst[s0 + t] : 0;
+        const int32_t ps = live && t > 0 ? src[s0 + t - 1] : 0, pd = live && t > 0 ? dst[s0 + t - 1] : 0;
+        uint64_t st[kWinStats];
+        st[0] = live ? (uint64_t)llabs((long long)vs - (long long)vd) : 0;
+        const bool pair = live && t > 0;
+        st[3] = pair && vs == ps;
+        st[4] = pair && vd == pd;
+        st[5] = pair && llabs((long long)vs - (long long)ps) < 32;
+        st[6] = pair && llabs((long long)vd - (long long)pd) < 32;
+        __syncthreads();
+        // distinct cache lines (id >> 5 < 2^27, never the empty marker)
+        for (int side = 0; side < 2; ++side) {
+            uint32_t *tb = tab + (side << kWinBits);
+            uint32_t fresh = 0;
+            if (live) {
+                const uint32_t k = (uint32_t)(side == 0 ? vs : vd) >> 5;
+                uint32_t h = fib_hash(k, kWinBits);
+                while (true) {
+                    const uint32_t prev = atomicCAS(&tb[h], kEmpty32, k);
+                    if (prev == kEmpty32) {
+                        fresh = 1;
+                        break;
+                    }
+                    if (prev == k) break;
+                    h = (h + 1) & ((1u << kWinBits) - 1);
+                }
+            }
+            st[1 + side] = fresh;
+        }
+        uint64_t *o = out + (size_t)blockIdx.x * kWinStats;
+        for (int q = 0; q < kWinStats; ++q) {
+            const uint64_t tot = block_sum64(st[q], red);
+            if (t == 0) o[q] = tot;
+        }
+        return;
     }
-    // carry the running max across threads
-    uint32_t total;
-    __shared__ uint32_t sl[kT / kWave];
-    const uint32_t before = block_exclusive_scan<kT>(run, OpMax{}, sl, total);
+    const uint32_t side = blockIdx.x - kWin;
+    const int32_t *arr = side == 0 ? src : dst;
+    for (uint32_t i = t; i < (1u << kSpreadBits); i += kT) {
+        key[i] = kEmpty64;
+        cnt[i] = 0;
+    }
+    __syncthreads();
+    for (uint32_t k = t; k < (uint32_t)kSpread; k += kT) {
+        const unsigned long long v = (uint32_t)arr[((uint64_t)k * m) / kSpread];
+        uint32_t h = fib_hash((uint32_t)v, kSpreadBits);
+        while (true) {
+            const unsigned long long prev = atomicCAS(&key[h], kEmpty64, v);
+            if (prev == kEmpty64 || prev == v) {
+                atomicAdd(&cnt[h], 1u);
+                break;
+            }
+            h = (h + 1) & ((1u << kSpreadBits) - 1);
+        }
+    }
+    __syncthreads();
     uint64_t coll = 0, distinct = 0;
     uint32_t mx = 0;
-    for (int q = 0; q < PER; ++q) {
-        const int i = threadIdx.x * PER + q;
-        const uint32_t s = max(before, loc[q]);
-        coll += (uint64_t)(i - s);            // earlier equal samples
-        mx = max(mx, (uint32_t)(i - s + 1));  // run length so far
-        distinct += s == (uint32_t)i;
+    for (uint32_t i = t; i < (1u << kSpreadBits); i += kT) {
+        const uint64_t c = cnt[i];
+        coll += c * (c - (c > 0)) / 2;  // c (c - 1) / 2 equal pairs
+        distinct += c > 0;
+        mx = max(mx, (uint32_t)c);
     }
     coll = block_sum64(coll, red);
     distinct = block_sum64(distinct, red);
     mx = block_max32(mx, red32);
-    if (threadIdx.x == 0) {
-        uint64_t *o = out + (size_t)kWin * kWinStats + blockIdx.x * kSpreadStats;
+    if (t == 0) {
+        uint64_t *o = out + (size_t)kWin * kWinStats + side * kSpreadStats;
         o[0] = coll;
         o[1] = mx;
         o[2] = distinct;
@@ -332,8 +333,7 @@ extern "C" boba_status boba_graph_features(const int32_t *src, const int32_t *ds
     uint64_t *st = (uint64_t *)ws;
     const uint32_t um = (uint32_t)m;
     if (m > 0) {
-        BOBA_LAUNCH("feat_windows", k_feat_windows, dim3(kWin), dim3(kT), stream, src, dst, um, st);
-        BOBA_LAUNCH("feat_spread", k_feat_spread, dim3(2), dim3(kT), stream, src, dst, um, st);
+        BOBA_LAUNCH("feat_stats", k_feat_stats, dim3(kWin + 2), dim3(kT), stream, src, dst, um, st);
     }
     BOBA_LAUNCH("feat_final", k_feat_final, dim3(1), dim3(64), stream, (const uint64_t *)st, um, (uint32_t)n, feat16);
     return BOBA_OK;

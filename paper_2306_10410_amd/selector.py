@@ -12,10 +12,10 @@ a feature or the prediction is not finite, the policy falls back to always
 reordering (the method itself).
 
 Labels are measured by the method itself on the GPU:
-    T_never  = t(coo_to_csr on input labels) + spmv_iters * t(spmv on it)
+    T_never  = t(coo_to_csr on input labels) + t(spmv_iters SpMVs on it)
     T_always = t(boba_reorder_relabel) + t(coo_to_csr on BOBA labels)
-               + spmv_iters * t(spmv on it)
-each the median of `reps` HIP-event timings.  Training uses the library's own
+               + t(spmv_iters SpMVs on it)
+each the median of `reps` HIP-event timings (the SpMVs run back to back).  Training uses the library's own
 backward and Adam kernels.
 """
 from __future__ import annotations
@@ -33,6 +33,9 @@ from . import graphgen
 
 N_FEAT = 16
 SPMV_ITERS = 20
+# Network trained on an MI355X by `python -m paper_2306_10410_amd.selector`
+# (4000 + 400 graphs, see main); timings, and so the model, are device-specific.
+DEFAULT_MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_model.npz")
 
 
 # --------------------------------------------------------------------- timing
@@ -58,26 +61,30 @@ def measure_paths(src, dst, val, x, n, *, reps=5, spmv_iters=SPMV_ITERS, ws=None
     ws_r = torch.empty(max(1, boba.boba_reorder_relabel_workspace(n, m)), dtype=torch.uint8, device=dev)
     ws_c = torch.empty(max(1, boba.coo_to_csr_workspace(n, m)), dtype=torch.uint8, device=dev)
     ws_s = torch.empty(max(1, boba.spmv_csr_workspace(n, m)), dtype=torch.uint8, device=dev)
+    # the SpMV iterations run back to back between two events, as a solver
+    # would run them
     t = {k: [] for k in ("csr_in", "spmv_in", "reorder_relabel", "csr_boba", "spmv_boba")}
     for _ in range(reps + 1):  # first round warms up
         e = _events(torch, 6)
         e[0].record()
         boba.coo_to_csr(src, dst, val, n, ws=ws_c, out=(rp, col, vv))
         e[1].record()
-        boba.spmv_csr(rp, col, vv, x, y=y, ws=ws_s)
+        for _ in range(spmv_iters):
+            boba.spmv_csr(rp, col, vv, x, y=y, ws=ws_s)
         e[2].record()
         boba.boba_reorder_relabel(src, dst, n, ws=ws_r, perm=perm, order=order, src_out=s2, dst_out=d2)
         e[3].record()
         boba.coo_to_csr(s2, d2, val, n, ws=ws_c, out=(rp, col, vv))
         e[4].record()
-        boba.spmv_csr(rp, col, vv, x, y=y, ws=ws_s)  # x in any labelling: same access pattern cost
+        for _ in range(spmv_iters):
+            boba.spmv_csr(rp, col, vv, x, y=y, ws=ws_s)  # x in any labelling: same access pattern cost
         e[5].record()
         torch.cuda.synchronize()
         for i, k in enumerate(t):
             t[k].append(e[i].elapsed_time(e[i + 1]))
     med = {k: float(np.median(v[1:])) for k, v in t.items()}
-    med["never"] = med["csr_in"] + spmv_iters * med["spmv_in"]
-    med["always"] = med["reorder_relabel"] + med["csr_boba"] + spmv_iters * med["spmv_boba"]
+    med["never"] = med["csr_in"] + med["spmv_in"]
+    med["always"] = med["reorder_relabel"] + med["csr_boba"] + med["spmv_boba"]
     return med
 
 
@@ -97,6 +104,22 @@ def start_pool(workers):
     import multiprocessing as mp
     from concurrent.futures import ProcessPoolExecutor
     return ProcessPoolExecutor(workers, mp_context=mp.get_context("fork"))
+
+
+def warm_up(log=None, seconds=2.0):
+    """Runs both paths on a mid-sized graph for a while, so that the timings
+    that follow see the GPU at its working clocks."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    g = graphgen.small_workload("rmat", 1 << 18, 1 << 22, graphgen.BASE_SEED + 55)
+    src, dst = torch.from_numpy(g.src).to(dev), torch.from_numpy(g.dst).to(dev)
+    val, x = torch.from_numpy(g.val).to(dev), torch.from_numpy(g.x).to(dev)
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        measure_paths(src, dst, val, x, g.n, reps=1)
+    if log:
+        log(f"warm-up {time.perf_counter() - t0:.1f}s")
 
 
 def build_dataset(specs, *, reps=5, log=None, pool=None):
@@ -205,29 +228,46 @@ def _digest(arrays):
     return h.hexdigest()
 
 
-def save_model(path, params, mu, sigma, meta=None):
-    np.savez(path, params=params.astype(np.float32), mu=mu, sigma=sigma, version=np.array([1]),
-             checksum=np.frombuffer(_digest([params.astype(np.float32), mu, sigma]).encode(), np.uint8),
+class Model:
+    """A deployable selector: MLP parameters on raw features and the size gate
+    (log2(1 + m) below which the graph is not reordered and no feature is
+    computed)."""
+
+    def __init__(self, params, gate=float("-inf")):
+        self.params = np.asarray(params, np.float32)
+        self.gate = float(gate)
+
+
+def save_model(path, params, mu, sigma, meta=None, gate=float("-inf")):
+    g = np.array([gate], np.float64)
+    p32 = params.astype(np.float32)
+    np.savez(path, params=p32, mu=mu, sigma=sigma, gate=g, version=np.array([2]),
+             checksum=np.frombuffer(_digest([p32, mu, sigma, g]).encode(), np.uint8),
              meta=np.frombuffer(json.dumps(meta or {}).encode(), np.uint8))
 
 
 def load_model(path):
-    """Returns params (float32[5313]) or None if the file is missing or invalid."""
+    """Returns a Model, or None if the file is missing or invalid (then the
+    policy falls back to always reordering)."""
     try:
         z = np.load(path, allow_pickle=False)
-        params, mu, sigma = z["params"], z["mu"], z["sigma"]
-        ok = (int(z["version"][0]) == 1 and params.shape == (5313,) and params.dtype == np.float32
-              and bytes(z["checksum"]).decode() == _digest([params, mu, sigma]) and np.all(np.isfinite(params)))
-        return params if ok else None
+        params, mu, sigma, gate = z["params"], z["mu"], z["sigma"], z["gate"]
+        ok = (int(z["version"][0]) == 2 and params.shape == (5313,) and params.dtype == np.float32
+              and gate.shape == (1,) and not np.isnan(gate[0])
+              and bytes(z["checksum"]).decode() == _digest([params, mu, sigma, gate])
+              and np.all(np.isfinite(params)))
+        return Model(params, gate[0]) if ok else None
     except Exception:
         return None
 
 
 class Selector:
-    """decide(src, dst, n) -> (reorder?, prediction).  Falls back to always
-    reordering when there is no usable model or the inputs are not finite."""
+    """decide(src, dst, n) -> (reorder?, prediction).  Graphs below the size
+    gate are not reordered (prediction -inf, no GPU work).  Falls back to
+    always reordering when there is no usable model or the prediction is not
+    finite."""
 
-    def __init__(self, params=None, device="cuda:0"):
+    def __init__(self, params=None, device="cuda:0", gate=float("-inf")):
         import torch
 
         from . import boba
@@ -235,17 +275,21 @@ class Selector:
         self.boba = boba
         self.dev = torch.device(device)
         self.params = None if params is None else torch.from_numpy(np.asarray(params, np.float32)).to(self.dev)
+        self.gate = float(gate)
         self.ws = torch.empty(boba.load().boba_graph_features_workspace(), dtype=torch.uint8, device=self.dev)
         self.feat = torch.empty(1, N_FEAT, dtype=torch.float32, device=self.dev)
         self.out = torch.empty(1, dtype=torch.float32, device=self.dev)
 
     @classmethod
-    def from_file(cls, path, device="cuda:0"):
-        return cls(load_model(path), device)
+    def from_file(cls, path=DEFAULT_MODEL, device="cuda:0"):
+        model = load_model(path)
+        return cls(None, device) if model is None else cls(model.params, device, model.gate)
 
     def decide(self, src, dst, n):
         if self.params is None:
             return True, float("nan")
+        if np.log2(1.0 + src.numel()) < self.gate:
+            return False, float("-inf")
         self.boba.boba_graph_features(src, dst, n, out=self.feat.view(-1), ws=self.ws)
         self.boba.boba_mlp_forward(self.params, self.feat, out=self.out)
         pred = float(self.out.cpu()[0])
@@ -254,9 +298,33 @@ class Selector:
         return pred > 0.0, pred
 
 
-def evaluate(params, X, rows, t_infer_ms):
+def _policy_totals(pred, rows, t_infer_ms, gate):
+    """Per-graph time of the gated policy: below the gate the input order is
+    kept (no feature work); above it features + inference + the MLP's choice
+    (a non-finite prediction reorders)."""
+    never = np.array([r["never"] for r in rows])
+    always = np.array([r["always"] for r in rows])
+    feat = np.array([r["t_feat"] for r in rows])
+    lm = np.log2(1.0 + np.array([r["m"] for r in rows], np.float64))
+    choose = np.where(np.isfinite(pred), pred > 0, True)
+    gated = lm < gate
+    t = np.where(gated, never, feat + t_infer_ms + np.where(choose, always, never))
+    return t, choose & ~gated
+
+
+def choose_gate(pred, rows, t_infer_ms):
+    """The size gate that minimises the policy's total time on the given
+    (training) graphs: every distinct log2(1 + m), and no gate."""
+    lm = np.log2(1.0 + np.array([r["m"] for r in rows], np.float64))
+    cands = np.concatenate([[-np.inf], np.unique(lm), [np.inf]])
+    best = min(cands, key=lambda g: float(_policy_totals(pred, rows, t_infer_ms, g)[0].sum()))
+    return float(best)
+
+
+def evaluate(params, X, rows, t_infer_ms, gate=float("-inf")):
     """Held-out totals: the selector's choice (plus its feature and inference
-    time) against the oracle choice, always-reorder and never-reorder."""
+    time above the gate) against the oracle choice, always-reorder and
+    never-reorder."""
     import torch
 
     from . import boba
@@ -265,17 +333,19 @@ def evaluate(params, X, rows, t_infer_ms):
     pred = boba.boba_mlp_forward(torch.from_numpy(params).to(dev), torch.from_numpy(X).to(dev)).cpu().numpy()
     never = np.array([r["never"] for r in rows])
     always = np.array([r["always"] for r in rows])
-    feat = np.array([r["t_feat"] for r in rows])
-    choose = np.where(np.isfinite(pred), pred > 0, True)
-    chosen = np.where(choose, always, never)
+    t_sel, choose = _policy_totals(pred, rows, t_infer_ms, gate)
+    t_nogate, choose_ng = _policy_totals(pred, rows, t_infer_ms, float("-inf"))
     opt = np.minimum(never, always)
-    sel_total = float(np.sum(feat + t_infer_ms + chosen))
-    return {"graphs": len(rows), "selector_ms": sel_total, "oracle_choice_ms": float(opt.sum()),
-            "always_ms": float(always.sum()), "never_ms": float(never.sum()),
+    sel_total = float(t_sel.sum())
+    return {"graphs": len(rows), "gate_log2m": gate, "selector_ms": sel_total,
+            "oracle_choice_ms": float(opt.sum()), "always_ms": float(always.sum()), "never_ms": float(never.sum()),
             "selector_vs_oracle": sel_total / float(opt.sum()),
             "selector_vs_always": sel_total / float(always.sum()),
+            "selector_vs_never": sel_total / float(never.sum()),
+            "ungated_selector_vs_oracle": float(t_nogate.sum()) / float(opt.sum()),
             "decisions_reorder": int(choose.sum()), "oracle_reorder": int((always < never).sum()),
-            "agreement": float(np.mean(choose == (always < never)))}
+            "agreement": float(np.mean(choose == (always < never))),
+            "mlp_agreement": float(np.mean(choose_ng == (always < never)))}
 
 
 def time_inference(params, reps=50):
@@ -320,19 +390,35 @@ def main(argv=None):
         ho_specs += selector_specs(max(1, k // 8), graphgen.BASE_SEED + 53, args.log2_hi, args.large_log2_hi)
     pool = start_pool(args.workers) if args.workers > 1 else None  # before the GPU is touched
     t0 = time.perf_counter()
-    Xtr, ytr, rtr = build_dataset(tr_specs, reps=args.reps, log=log, pool=pool)
-    Xho, yho, rho = build_dataset(ho_specs, reps=args.reps, log=log, pool=pool)
+    warm_up(log)
+    # training and held-out graphs are measured interleaved, so that slow
+    # drifts of the machine do not separate the two sets
+    specs = tr_specs + ho_specs
+    order = np.random.default_rng(graphgen.BASE_SEED + 54).permutation(len(specs))
+    X, y, rows = build_dataset([specs[i] for i in order], reps=args.reps, log=log, pool=pool)
+    inv = np.empty_like(order)
+    inv[order] = np.arange(len(order))
+    X, y, rows = X[inv], y[inv], [rows[i] for i in inv]
+    ntr = len(tr_specs)
+    Xtr, ytr, rtr = X[:ntr], y[:ntr], rows[:ntr]
+    Xho, yho, rho = X[ntr:], y[ntr:], rows[ntr:]
     if pool is not None:
         pool.shutdown()
     log(f"datasets in {time.perf_counter() - t0:.1f}s; train labels: {np.mean(ytr > 0):.3f} reorder-pays")
     params, mu, sigma, hist = train(Xtr, ytr, epochs=args.epochs, log=log)
+    t_inf = time_inference(params)
+    import torch
+
+    from . import boba
+    pred_tr = boba.boba_mlp_forward(torch.from_numpy(params).cuda(), torch.from_numpy(Xtr).cuda()).cpu().numpy()
+    gate = choose_gate(pred_tr, rtr, t_inf)
+    log(f"size gate: log2(1 + m) >= {gate:.3f}")
     os.makedirs(os.path.dirname(args.out) or ".", exist_ok=True)
-    save_model(args.out, params, mu, sigma, {"train": args.train, "epochs": args.epochs})
+    save_model(args.out, params, mu, sigma, {"train": args.train, "epochs": args.epochs}, gate=gate)
     np.savez(args.data_out, Xtr=Xtr, ytr=ytr, Xho=Xho, yho=yho,
              rows_tr=np.frombuffer(json.dumps(rtr).encode(), np.uint8),
              rows_ho=np.frombuffer(json.dumps(rho).encode(), np.uint8))
-    t_inf = time_inference(params)
-    res = evaluate(params, Xho, rho, t_inf)
+    res = evaluate(params, Xho, rho, t_inf, gate)
     res.update({"train_graphs": args.train, "train_mse": hist[-1], "t_infer_ms": t_inf,
                 "t_feat_ms_median": float(np.median([r["t_feat"] for r in rho]))})
     print(json.dumps(res), flush=True)

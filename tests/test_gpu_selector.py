@@ -98,3 +98,7 @@ def test_selector_decision_and_fallback():
     bad = p.copy()
     bad[-1] = np.nan
     assert selector.Selector(bad).decide(s, d, g.n)[0] is True  # non-finite prediction: fallback
+    # below the size gate: keep the input order, no feature work
+    gated = selector.Selector(p, gate=np.log2(1.0 + g.m) + 0.1)
+    assert gated.decide(s, d, g.n) == (False, float("-inf"))
+    assert selector.Selector(p, gate=np.log2(1.0 + g.m) - 0.1).decide(s, d, g.n)[0] == choice
