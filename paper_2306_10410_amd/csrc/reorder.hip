@@ -545,10 +545,12 @@ __global__ __launch_bounds__(kSplitThreads) void k_tile_unsplit(const uint32_t *
 // in the tail).  Keys below 2m are grouped into key blocks of 2^kbits
 // positions (about 4096 blocks); the isolated vertices form one extra block
 // after them.
-//   rank_count    per vertex bucket: its vertices per key block (LDS counters)
-//   scan          exclusive scan, block-major: where bucket b's entries of key
-//                 block k start in the entry list E (and how many keys precede
-//                 the block)
+//   rank_count    per vertex bucket: its vertices per key block (LDS counters),
+//                 stored bucket-major
+//   scan          transposed to block-major, exclusive scan: where bucket b's
+//                 entries of key block k start in the entry list E (and how
+//                 many keys precede the block); transposed back for the
+//                 per-bucket kernels
 //   rank_scatter  per vertex bucket: {r, v} of every occurring vertex into E
 //   rank_block    per key block: its keys as an LDS bitmap with prefix
 //                 popcounts; rank = keys in earlier blocks + keys before it in
@@ -557,9 +559,9 @@ __global__ __launch_bounds__(kSplitThreads) void k_tile_unsplit(const uint32_t *
 //                 isolated vertices take the tail ranks in increasing ID
 // Every step streams or works in LDS: no device-wide random atomics.
 constexpr uint32_t kMinKeyBits = 15;
-constexpr uint32_t kMaxKeyBits = 19;
+constexpr uint32_t kMaxKeyBits = 18;                            // rank_block LDS <= 48 KB
 constexpr uint32_t kTargetKeyBlocks = 4096;                    // bounds a key block's entries
-constexpr uint32_t kMaxKeyBlocks = 2 * kTargetKeyBlocks;       // 2m < 2^32 at 2^19 positions per block
+constexpr uint32_t kMaxKeyBlocks = 1u << (32 - kMaxKeyBits);    // 2m < 2^32
 
 __device__ __forceinline__ uint32_t merged_r(const uint32_t *__restrict__ rpart, uint32_t slices, uint32_t n,
                                              uint32_t v) {
@@ -568,9 +570,11 @@ __device__ __forceinline__ uint32_t merged_r(const uint32_t *__restrict__ rpart,
     return p;
 }
 
+// cnt_b[b][k]: bucket-major (coalesced rows); cnt gets its final zero, where
+// the scan of the transposed counts leaves the total.
 __global__ __launch_bounds__(kMinThreads) void k_rank_count(const uint32_t *__restrict__ rpart, uint32_t slices,
                                                             uint32_t n, uint32_t nb, uint32_t nblk, uint32_t kbits,
-                                                            uint32_t *__restrict__ cnt) {
+                                                            uint32_t *__restrict__ cnt_b, uint32_t *__restrict__ cnt) {
     __shared__ uint32_t h[kMaxKeyBlocks + 1];
     const uint32_t b = blockIdx.x;
     const uint32_t v0 = b * kBucketW;
@@ -589,17 +593,17 @@ __global__ __launch_bounds__(kMinThreads) void k_rank_count(const uint32_t *__re
         if (i < cntv && !iso) atomicAdd(&h[p >> kbits], 1u);
     }
     __syncthreads();
-    for (uint32_t k = threadIdx.x; k <= nblk; k += kMinThreads) cnt[(size_t)k * nb + b] = h[k];
+    for (uint32_t k = threadIdx.x; k <= nblk; k += kMinThreads) cnt_b[(size_t)b * (nblk + 1) + k] = h[k];
 }
 
 __global__ __launch_bounds__(kMinThreads) void k_rank_scatter(const uint32_t *__restrict__ rpart, uint32_t slices,
-                                                              uint32_t n, uint32_t nb, uint32_t nblk, uint32_t kbits,
-                                                              const uint32_t *__restrict__ off, uint2 *__restrict__ E) {
+                                                              uint32_t n, uint32_t nblk, uint32_t kbits,
+                                                              const uint32_t *__restrict__ off_b, uint2 *__restrict__ E) {
     __shared__ uint32_t cur[kMaxKeyBlocks];
     const uint32_t b = blockIdx.x;
     const uint32_t v0 = b * kBucketW;
     const uint32_t cntv = min(kBucketW, n - v0);
-    for (uint32_t k = threadIdx.x; k < nblk; k += kMinThreads) cur[k] = off[(size_t)k * nb + b];
+    for (uint32_t k = threadIdx.x; k < nblk; k += kMinThreads) cur[k] = off_b[(size_t)b * (nblk + 1) + k];
     __syncthreads();
     constexpr int U = 8;
     for (uint32_t i0 = threadIdx.x; i0 < cntv; i0 += U * kMinThreads) {
@@ -619,36 +623,46 @@ __global__ __launch_bounds__(kMinThreads) void k_rank_scatter(const uint32_t *__
     }
 }
 
-__global__ __launch_bounds__(kMinThreads) void k_rank_block(const uint2 *__restrict__ E,
-                                                            const uint32_t *__restrict__ off, uint32_t nb,
-                                                            uint32_t kbits, uint32_t *__restrict__ Rk,
-                                                            int32_t *__restrict__ order) {
-    __shared__ uint32_t bits[1u << (kMaxKeyBits - 5)];
-    __shared__ uint16_t pre[1u << (kMaxKeyBits - 5)];   // exclusive popcount within a 64-word group
-    __shared__ uint32_t gbase[1u << (kMaxKeyBits - 11)];  // exclusive popcount of the groups
-    __shared__ uint32_t scan_lds[kMinThreads / kWave];
+// One 1024-thread workgroup per key block, LDS sized to the block (dynamic):
+// bits[2^(kbits-5)], then uint16 pre[same], then uint32 gbase[2^(kbits-11)].
+// At 2^17 positions per block that is 24 KB, so two blocks share a CU.
+constexpr int kRankThreads = 1024;
+
+inline size_t rank_block_lds(uint32_t kbits) {
+    const size_t words = (size_t)1 << (kbits - 5);
+    return words * 4 + words * 2 + (words / kWave) * 4;
+}
+
+__global__ __launch_bounds__(kRankThreads) void k_rank_block(const uint2 *__restrict__ E,
+                                                             const uint32_t *__restrict__ off, uint32_t nb,
+                                                             uint32_t kbits, uint32_t *__restrict__ Rk,
+                                                             int32_t *__restrict__ order) {
+    extern __shared__ __align__(16) uint32_t dyn[];
+    const uint32_t nwords = 1u << (kbits - 5);
+    const uint32_t ngroups = nwords / kWave;  // 16 .. 256
+    uint32_t *bits = dyn;
+    uint16_t *pre = (uint16_t *)(dyn + nwords);      // exclusive popcount within a 64-word group
+    uint32_t *gbase = dyn + nwords + nwords / 2;     // exclusive popcount of the groups
     const uint32_t blk = xcd_work_index(blockIdx.x, gridDim.x);
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = threadIdx.x / kWave;
-    constexpr uint32_t NWAVE = kMinThreads / kWave;
-    const uint32_t nwords = 1u << (kbits - 5);
-    const uint32_t ngroups = nwords / kWave;
-    for (uint32_t i = threadIdx.x; i < nwords; i += kMinThreads) bits[i] = 0;
+    constexpr uint32_t NWAVE = kRankThreads / kWave;
+    for (uint32_t i = threadIdx.x; i < nwords; i += kRankThreads) bits[i] = 0;
     __syncthreads();
     const uint32_t e0 = off[(size_t)blk * nb];
     const uint32_t e1 = off[(size_t)(blk + 1) * nb];
     const uint32_t base = blk << kbits;
     constexpr int U = 8;  // entries in flight per thread
-    for (uint32_t e = e0 + threadIdx.x; e < e1; e += U * kMinThreads) {
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += U * kRankThreads) {
         uint32_t p[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const uint32_t i = e + u * kMinThreads;
+            const uint32_t i = e + u * kRankThreads;
             p[u] = i < e1 ? E[i].x - base : 0u;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (e + u * kMinThreads < e1) atomicOr(&bits[p[u] >> 5], 1u << (p[u] & 31));
+            if (e + u * kRankThreads < e1) atomicOr(&bits[p[u] >> 5], 1u << (p[u] & 31));
     }
     __syncthreads();
     for (uint32_t g = wave; g < ngroups; g += NWAVE) {
@@ -659,36 +673,55 @@ __global__ __launch_bounds__(kMinThreads) void k_rank_block(const uint2 *__restr
         if (lane == kWave - 1) gbase[g] = incl;
     }
     __syncthreads();
-    uint32_t total;
-    const uint32_t gs = threadIdx.x < ngroups ? gbase[threadIdx.x] : 0u;
-    const uint32_t gex = block_exclusive_scan<kMinThreads>(gs, OpSum{}, scan_lds, total);
-    if (threadIdx.x < ngroups) gbase[threadIdx.x] = gex;
+    // exclusive scan of the group sums (at most 256 groups): one wave, four per lane
+    if (wave == 0) {
+        uint32_t v[4], t = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t g = lane * 4 + q;
+            v[q] = g < ngroups ? gbase[g] : 0u;
+            t += v[q];
+        }
+        uint32_t run = wave_inclusive_scan(t, OpSum{}) - t;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t g = lane * 4 + q;
+            if (g < ngroups) gbase[g] = run;
+            run += v[q];
+        }
+    }
     __syncthreads();
-    for (uint32_t e = e0 + threadIdx.x; e < e1; e += U * kMinThreads) {
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += U * kRankThreads) {
         uint2 x[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const uint32_t i = e + u * kMinThreads;
+            const uint32_t i = e + u * kRankThreads;
             x[u] = i < e1 ? E[i] : make_uint2(base, 0u);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const uint32_t i = e + u * kMinThreads;
-            if (i >= e1) continue;
+            if (e + u * kRankThreads >= e1) continue;
             const uint32_t p = x[u].x - base;
             const uint32_t w = p >> 5;
             const uint32_t k = e0 + gbase[w / kWave] + pre[w] + __popc(bits[w] & ((1u << (p & 31)) - 1u));
-            Rk[i] = k;
-            if (order) order[k] = (int32_t)x[u].y;
+            Rk[e + u * kRankThreads] = k;  // beside the entry (coalesced)
+            if (order) order[k] = (int32_t)x[u].y;  // within the block's rank range
         }
     }
 }
 
+// Per vertex bucket: the ranks of its occurring vertices come back from the
+// entry list into an LDS perm slice (segment bounds 64 at a time, the first 64
+// entries of 8 segments in flight); isolated vertices (still unset) take the
+// tail ranks from iso_base on in increasing ID, via one ballot bitmap and one
+// scan; the slice is written out coalesced.
 __global__ __launch_bounds__(kMinThreads) void k_rank_perm(const uint2 *__restrict__ E, const uint32_t *__restrict__ Rk,
-                                                           const uint32_t *__restrict__ off, uint32_t nb,
-                                                           uint32_t nblk, uint32_t n, int32_t *__restrict__ perm,
+                                                           const uint32_t *__restrict__ off_b,
+                                                           const uint32_t *__restrict__ cnt_b, uint32_t nblk,
+                                                           uint32_t n, int32_t *__restrict__ perm,
                                                            int32_t *__restrict__ order) {
     __shared__ uint32_t lp[kBucketW];
+    __shared__ uint32_t flags[kBucketW / 32];
     __shared__ uint32_t scan_lds[kMinThreads / kWave];
     const uint32_t b = blockIdx.x;
     const uint32_t v0 = b * kBucketW;
@@ -698,14 +731,13 @@ __global__ __launch_bounds__(kMinThreads) void k_rank_perm(const uint2 *__restri
     constexpr uint32_t NWAVE = kMinThreads / kWave;
     for (uint32_t i = threadIdx.x; i < kBucketW; i += kMinThreads) lp[i] = kInf;
     __syncthreads();
-    // wave w takes key blocks [64 w', 64 w' + 64) for w' = w, w + 16, ...: one
-    // coalesced-ish load of 64 segment bounds, then the first 64 entries of 8
-    // segments at a time; longer segments finish in a loop
     constexpr int U = 8;
+    const uint32_t *ob = off_b + (size_t)b * (nblk + 1);
+    const uint32_t *cb = cnt_b + (size_t)b * (nblk + 1);
     for (uint32_t g = wave * kWave; g < nblk; g += NWAVE * kWave) {
         const uint32_t my = g + lane;
-        const uint32_t sb = my < nblk ? off[(size_t)my * nb + b] : 0u;
-        const uint32_t se = my < nblk ? off[(size_t)my * nb + b + 1] : 0u;
+        const uint32_t sb = my < nblk ? ob[my] : 0u;
+        const uint32_t se = my < nblk ? sb + cb[my] : 0u;
         const uint32_t cnt = min((uint32_t)kWave, nblk - g);
         for (uint32_t j0 = 0; j0 < cnt; j0 += U) {
             uint32_t vv[U], rk[U];
@@ -730,19 +762,27 @@ __global__ __launch_bounds__(kMinThreads) void k_rank_perm(const uint2 *__restri
         }
     }
     __syncthreads();
-    const uint32_t iso_base = off[(size_t)nblk * nb + b];
-    uint32_t carry = 0;
-    for (uint32_t q = 0; q < kBucketW; q += kMinThreads) {
-        const uint32_t i = q + threadIdx.x;
-        const bool iso = i < cntv && lp[i] == kInf;
-        uint32_t tot;
-        const uint32_t ex = block_exclusive_scan<kMinThreads>(iso ? 1u : 0u, OpSum{}, scan_lds, tot);
-        if (iso) {
-            const uint32_t k = iso_base + carry + ex;
-            lp[i] = k;
-            if (order) order[k] = (int32_t)(v0 + i);
+    // isolated flags: vertices [u*1024 + wave*64, +64) -> words 32u + 2 wave, +1
+    for (uint32_t u = 0; u < kBucketW / kMinThreads; ++u) {
+        const uint32_t i = u * kMinThreads + threadIdx.x;
+        const uint64_t bal = __ballot(i < cntv && lp[i] == kInf);
+        if (lane == 0) {
+            const uint32_t w = (u * kMinThreads + wave * kWave) / 32;
+            flags[w] = (uint32_t)bal;
+            flags[w + 1] = (uint32_t)(bal >> 32);
         }
-        carry += tot;
+    }
+    __syncthreads();
+    const uint32_t word = flags[threadIdx.x];  // vertices 32 t .. 32 t + 31
+    uint32_t tot;
+    const uint32_t before = block_exclusive_scan<kMinThreads>(__popc(word), OpSum{}, scan_lds, tot);
+    uint32_t left = word, k = ob[nblk] + before;
+    while (left) {
+        const uint32_t j = __ffs(left) - 1;
+        left &= left - 1;
+        lp[threadIdx.x * 32 + j] = k;
+        if (order) order[k] = (int32_t)(v0 + threadIdx.x * 32 + j);
+        ++k;
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < cntv; i += kMinThreads) perm[v0 + i] = (int32_t)lp[i];
@@ -765,12 +805,18 @@ ReorderPlan reorder_plan(int64_t n, int64_t m) {
     P.bucketed = m > 0 && n > 0 && P.nb <= kMaxBuckets;
     P.slices = 1;
     if (P.bucketed) {
-        // about 256 workgroups for the bucket pass (one per CU)
-        uint32_t s = ceil_div(256, P.nb);
-        P.slices = s < P.nt ? s : P.nt;
+        // Enough (bucket, slice) workgroups to fill 256 CUs; up to four per CU
+        // so that uneven buckets (hubs of a power-law graph land in a few) are
+        // balanced by the dispatcher, as long as the partial minima (slices x
+        // 4n bytes) stay below an eighth of the record traffic (8m bytes).
+        const uint64_t fill = ceil_div(256, P.nb), spread = ceil_div(1024, P.nb);
+        const uint64_t cap = (uint64_t)m / (4 * (uint64_t)n) > 1 ? (uint64_t)m / (4 * (uint64_t)n) : 1;
+        uint64_t s = spread < cap ? spread : cap;
+        if (s < fill) s = fill;
+        P.slices = (uint32_t)(s < P.nt ? s : P.nt);
         if (P.slices < 1) P.slices = 1;
         P.region = split_region(P.nb);
-        // about 4096 key blocks of 2^15 .. 2^19 positions: the first blocks of
+        // about 4096 key blocks of 2^15 .. 2^18 positions: the first blocks of
         // a graph hold most first occurrences, and a small block bounds the
         // work of the workgroup that ranks it
         const uint64_t keys = 2 * (uint64_t)m;
@@ -788,7 +834,7 @@ struct ReorderLayout {
     uint32_t *partial;
     uint32_t *recs, *tile_off, *off_t;
     uint32_t *vals;  // new IDs in record layout (fused relabel only)
-    uint32_t *cnt, *cnt_partial, *Rk;  // bucketed ranking
+    uint32_t *cnt, *cnt_b, *off_b, *cnt_partial, *Rk;  // bucketed ranking
     uint2 *E;
     uint32_t ncnt;
     size_t bytes;
@@ -809,6 +855,8 @@ ReorderLayout reorder_layout(void *ws, int64_t n, int64_t m, const ReorderPlan &
     L.vals = c.take<uint32_t>(P.bucketed && with_vals ? (size_t)P.nt * P.region : 0);
     L.ncnt = P.bucketed ? (P.nblk + 1) * P.nb + 1 : 0;
     L.cnt = c.take<uint32_t>(L.ncnt);
+    L.cnt_b = c.take<uint32_t>(P.bucketed ? L.ncnt - 1 : 0);
+    L.off_b = c.take<uint32_t>(P.bucketed ? L.ncnt - 1 : 0);
     L.cnt_partial = c.take<uint32_t>(P.bucketed ? scan_partials(L.ncnt) : 0);
     L.E = c.take<uint2>(P.bucketed ? (size_t)n : 0);
     L.Rk = c.take<uint32_t>(P.bucketed ? (size_t)n : 0);
@@ -848,17 +896,30 @@ boba_status reorder_run(const int32_t *src, const int32_t *dst, uint32_t um, uin
         BOBA_LAUNCH("bucket_min", k_bucket_min, dim3(P.nb * P.slices), dim3(kMinThreads), stream,
                     (const uint32_t *)L.recs, (const uint32_t *)L.off_t, P.nt, P.tiles_half, P.region, P.nb, P.tps,
                     min_batch(P), un, inter ? 1u : um, inter ? 2u : 1u, L.r);
+        const uint32_t kcols = P.nblk + 1;  // key blocks and the tail block
         BOBA_LAUNCH("rank_count", k_rank_count, dim3(P.nb), dim3(kMinThreads), stream, (const uint32_t *)L.r,
-                    P.slices, un, P.nb, P.nblk, P.kbits, L.cnt);
+                    P.slices, un, P.nb, P.nblk, P.kbits, L.cnt_b, L.cnt);
+        // bucket-major counts -> block-major, scanned in place -> bucket-major offsets
+        BOBA_LAUNCH("rank_transpose", k_transpose, dim3(ceil_div(kcols, 32), ceil_div(P.nb, 32)), dim3(256), stream,
+                    (const uint32_t *)L.cnt_b, P.nb, kcols, L.cnt);
         if (boba_status e = device_scan<OpSum, false>("rank_scan", LoadArr{L.cnt}, StoreArr{L.cnt}, L.ncnt,
                                                       L.cnt_partial, stream))
             return e;
+        BOBA_LAUNCH("rank_transpose", k_transpose, dim3(ceil_div(P.nb, 32), ceil_div(kcols, 32)), dim3(256), stream,
+                    (const uint32_t *)L.cnt, kcols, P.nb, L.off_b);
         BOBA_LAUNCH("rank_scatter", k_rank_scatter, dim3(P.nb), dim3(kMinThreads), stream, (const uint32_t *)L.r,
-                    P.slices, un, P.nb, P.nblk, P.kbits, (const uint32_t *)L.cnt, L.E);
-        BOBA_LAUNCH("rank_block", k_rank_block, dim3(P.nblk), dim3(kMinThreads), stream, (const uint2 *)L.E,
-                    (const uint32_t *)L.cnt, P.nb, P.kbits, L.Rk, order);
+                    P.slices, un, P.nblk, P.kbits, (const uint32_t *)L.off_b, L.E);
+        {
+            const size_t lds = rank_block_lds(P.kbits);
+            const int tok = timing_begin("rank_block", stream);
+            hipLaunchKernelGGL(k_rank_block, dim3(P.nblk), dim3(kRankThreads), lds, stream, (const uint2 *)L.E,
+                               (const uint32_t *)L.cnt, P.nb, P.kbits, L.Rk, order);
+            timing_end(tok, stream);
+            if (boba_status e = check_launch("rank_block")) return e;
+        }
         BOBA_LAUNCH("rank_perm", k_rank_perm, dim3(P.nb), dim3(kMinThreads), stream, (const uint2 *)L.E,
-                    (const uint32_t *)L.Rk, (const uint32_t *)L.cnt, P.nb, P.nblk, un, perm, order);
+                    (const uint32_t *)L.Rk, (const uint32_t *)L.off_b, (const uint32_t *)L.cnt_b, P.nblk, un, perm,
+                    order);
         return BOBA_OK;
     } else {
         BOBA_LAUNCH("reorder_init", k_reorder_init, dim3(grid_for(un > L.nw ? un : L.nw, kBlock * 4)),

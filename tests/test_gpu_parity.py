@@ -256,7 +256,7 @@ def test_fused_reorder_relabel_in_place_and_unaligned():
     assert boba.boba_check_device_error() == boba.BOBA_OK
 
 
-# The bucketed ranking groups first positions into key blocks of 2^15 .. 2^19
+# The bucketed ranking groups first positions into key blocks of 2^15 .. 2^18
 # positions (about 4096 blocks); these sizes give one block, a few, 1025, 4097
 # (2^15 positions each) and 2051 (2^16), with ragged last blocks and buckets.
 # RMAT-24 (2^17-position blocks) is in the full-scale tests.
