@@ -56,14 +56,23 @@ __global__ __launch_bounds__(kHistThreads) void k_radix_hist(const int32_t *__re
             for (int q = 0; q < 4; ++q) k[4 * j + q] = e + q < m ? (uint32_t)keys[e + q] : 0u;
         }
     }
+    // Digit 0 is counted in a register: after BOBA the smallest row IDs are
+    // the hubs, so in the upper digits 0 is by far the most frequent, and
+    // equal-address LDS atomics from one wave serialize.
+    uint32_t zeros = 0;
 #pragma unroll
     for (int j = 0; j < kHistPer / 4; ++j) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            if (base + j * (4 * kHistThreads) + 4 * threadIdx.x + q < m)
-                atomicAdd(&h[wave][(k[4 * j + q] >> shift) & (BINS - 1)], 1u);
+            if (base + j * (4 * kHistThreads) + 4 * threadIdx.x + q < m) {
+                const uint32_t d = (k[4 * j + q] >> shift) & (BINS - 1);
+                if (d == 0) ++zeros;
+                else atomicAdd(&h[wave][d], 1u);
+            }
         }
     }
+    zeros = wave_reduce(zeros, OpSum{});
+    if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&h[wave][0], zeros);
     __syncthreads();
     for (uint32_t d = threadIdx.x; d < BINS; d += kHistThreads) {
         uint32_t t = 0;
