@@ -1,0 +1,63 @@
+"""Host-side pieces of the benchmark and the tuner (no GPU needed)."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]
+
+
+def test_algorithmic_bytes_table():
+    n, m = 1 << 24, 1 << 28
+    assert bench.kernel_alg_bytes("bucket_split", n, m) == 16 * m
+    assert bench.kernel_alg_bytes("radix_scatter", n, m) == 24 * m
+    assert bench.kernel_alg_bytes("spmv", n, m) == 8 * m + 4 * (n + 1) + 8 * n
+    assert bench.kernel_alg_bytes("no_such_kernel", n, m) is None
+
+
+def test_pmc_traffic_requires_a_matching_source_digest(tmp_path, monkeypatch):
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "source_digest", lambda: "abc123")
+    (prof / "pmc_k_radix_scatter_w.txt").write_text("# x\nsource_digest: abc123\nhbm_bytes_per_launch: 42\n")
+    assert bench.pmc_traffic("radix_scatter", "w", 3) == 42.0
+    (prof / "pmc_k_radix_scatter_w.txt").write_text("source_digest: stale\nhbm_bytes_per_launch: 42\n")
+    assert bench.pmc_traffic("radix_scatter", "w", 3) is None
+    assert bench.pmc_traffic("spmv", "w", 1) is None  # no summary
+
+
+def test_committed_profiles_name_their_command():
+    prof = os.path.join(ROOT, "profiles")
+    files = [f for f in os.listdir(prof) if f.endswith(".txt")]
+    assert files
+    for f in files:
+        text = open(os.path.join(prof, f)).read()
+        assert "rocprofv3" in text and "bench.py" in text and "source_digest:" in text, f
+
+
+def test_tuner_cache_key_and_struct(monkeypatch, tmp_path):
+    pytest.importorskip("torch")
+    from paper_2306_10410_amd import tune
+    monkeypatch.setenv("BOBA_TUNE_CACHE", str(tmp_path / "c.json"))
+    key = tune.batch_key([0, 1000, 3000], [0, 100, 300])
+    assert key.endswith("|G2^1|m2^12|n2^8")
+    tune._store_cache({"k": {"tuning": tune.DEFAULT, "ms": 1.0}})
+    assert tune._load_cache()["k"]["tuning"] == tune.DEFAULT
+    st = tune.to_struct(tune.DEFAULT)
+    assert (st.small_max_n, st.scatter_tile) == (tune.DEFAULT["small_max_n"], tune.DEFAULT["scatter_tile"])
+    for name, values in tune.GRID.items():
+        assert tune.DEFAULT[name] in values, name
