@@ -1,17 +1,25 @@
 // BOBA reordering (Sec. 4.4, Algorithm 2 with AtomicMin) and edge relabelling.
 //
-// Pipeline of boba_reorder on one stream:
-//   init      r[v] <- inf, bitmap <- 0
-//   scatter   for every position i of the flattened edge list S = I ++ J,
-//             r[S[i]] <- min(r[S[i]], i)          (Algorithm 2, lines with r)
-//             either directly (one global atomic min per new position) or,
-//             for graphs up to 2^25 vertices, bucketed through LDS (below)
-//   mark      key(v) = r[v], or 2m + v when v never occurs (tail); set bit
-//             key(v) in a bitmap over [0, 2m + n)
-//   scan      prefix popcount of the bitmap words      } ParMapKeys: the rank
-//   rank      perm[v] = number of set bits before key(v) } of each unique key
-// The bitmap holds, per 32 positions, {bits, exclusive prefix popcount} as one
-// uint2 so that rank needs one 8-byte load per vertex.
+// boba_reorder computes, for every vertex v, r[v] = its first position in the
+// flattened edge list S = I ++ J (Algorithm 2, the lines that write r, with an
+// exact minimum), then perm[v] = the rank of key(v) = r[v] among all keys, where
+// a vertex that never occurs has key 2m + v (it follows all others in
+// increasing ID).  Two paths:
+//   bucketed (n <= 2^25, 16-byte aligned src/dst; the normal case)
+//     split     per tile of S, records {offset, v mod 2^15} sorted by vertex
+//               bucket (v >> 15) in LDS, written segment by segment
+//     min       per (bucket, slice): the bucket's r in LDS, every record folded
+//               in with an LDS minimum
+//     rank      keys grouped by key block, each block ranked with an LDS
+//               bitmap and prefix popcounts (ParMapKeys without a hash table)
+//   direct (otherwise)
+//     init      r[v] <- inf, bitmap <- 0
+//     scatter   r[S[i]] <- min(r[S[i]], i), one global atomic per new position
+//     mark      set bit key(v) in a bitmap over [0, 2m + n)
+//     scan      prefix popcount of the bitmap words
+//     rank      perm[v] = number of set bits before key(v)
+//   The direct path's bitmap holds, per 32 positions, {bits, exclusive prefix
+//   popcount} as one uint2 so that rank needs one 8-byte load per vertex.
 #include "internal.h"
 #include "scan.h"
 
