@@ -73,3 +73,22 @@ def test_grid4096_restores_row_major_labels():
     # closed form: every vertex occurs as a source in original row-major order
     assert np.array_equal(ph[sigma], np.arange(side * side, dtype=np.int32))
     assert np.array_equal(ph, oracle.boba(s, d, side * side)[0])
+
+
+def test_largest_bucketed_graph():
+    # the bucketed path's limits: n = 2^25 vertices (1024 LDS buckets), and
+    # m = 2^30 - 5 edges (2m + n < 2^32 positions, 65,536 tiles, ragged tail)
+    n, m = 1 << 25, (1 << 30) - 5
+    rng = np.random.default_rng(97)
+    src = rng.integers(0, n, m, dtype=np.int32)
+    dst = rng.integers(0, n, m, dtype=np.int32)
+    s, d = dev(src), dev(dst)
+    perm, order, s2, d2 = boba.boba_reorder_relabel(s, d, n)
+    p_ref, o_ref = oracle.boba(src, dst, n)
+    assert np.array_equal(host(perm), p_ref) and np.array_equal(host(order), o_ref)
+    del s, d
+    # relabel on sampled edges (the whole arrays would double host memory)
+    idx = rng.integers(0, m, 1 << 22)
+    ti = torch.from_numpy(idx).cuda()
+    assert np.array_equal(host(s2[ti]), p_ref[src[idx]]) and np.array_equal(host(d2[ti]), p_ref[dst[idx]])
+    assert boba.boba_check_device_error() == boba.BOBA_OK
