@@ -147,6 +147,9 @@ def main():
     ap.add_argument("--before-reps", type=int, default=5)
     ap.add_argument("--batch-graphs", type=int, default=512, help="graphs in the batched measurement (0: skip)")
     ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--bin-bits", type=int, default=8,
+                    help="also time binning the edges by destination into 2^B bins before BOBA (0: skip)")
+    ap.add_argument("--shuffle-edges", action="store_true", help="put the workload's edges in random order first")
     ap.add_argument("--calibrate", action="store_true",
                     help="run a plain elementwise kernel over 256 MiB (reads and writes 256 MiB) first, "
                          "to scale hardware byte counters")
@@ -167,6 +170,8 @@ def main():
     log(f"generating {args.workload}")
     t0 = time.perf_counter()
     g = graphgen.make_workload(args.workload)
+    if args.shuffle_edges:
+        g.src, g.dst = graphgen.shuffle_edges(g.src, g.dst, graphgen.BASE_SEED + 2)
     n, m = g.n, g.m
     log(f"n={n} m={m} generated in {time.perf_counter() - t0:.1f}s")
     batch = None
@@ -294,6 +299,10 @@ def main():
     spmv_agree = float(np.linalg.norm(ya - yb) / max(np.linalg.norm(yb), 1e-30))
     assert boba.boba_check_device_error() == boba.BOBA_OK
 
+    binned = None
+    if args.bin_bits > 0:
+        binned = bench_binned(args, g, src, dst, val, x, dev, ws_rr, ws_c, ws_s, before_spmv_ms)
+
     kernels = {}
     for name, (tot, cnt) in list(kern.items()) + [(f"{k} [boba_reorder alone]", v) for k, v in reorder_kern.items()]:
         per_step = cnt / args.steps
@@ -354,12 +363,60 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched": batched,
+        "binned": binned,
         "paper_context": PAPER_CONTEXT,
         "device": torch.cuda.get_device_name(0),
         "source_digest": source_digest(),
     }
     print(json.dumps(out), flush=True)
     return 0
+
+
+def bench_binned(args, g, src, dst, val, x, dev, ws_rr, ws_c, ws_s, before_spmv_ms, reps=5):
+    """Sec. 5.6's remedy for edges in random order: bin the edge list by
+    destination, then BOBA, CSR and SpMV on the binned list."""
+    import numpy as np
+    import torch
+
+    from paper_2306_10410_amd import boba
+
+    n, m = g.n, g.m
+    log(f"binned leg: 2^{args.bin_bits} destination bins")
+    sb, db = torch.empty_like(src), torch.empty_like(dst)
+    ws_b = torch.empty(boba.boba_bin_by_dst_workspace(n, m), dtype=torch.uint8, device=dev)
+    perm = torch.empty(n, dtype=torch.int32, device=dev)
+    s2, d2 = torch.empty_like(src), torch.empty_like(dst)
+    rowptr = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    col = torch.empty(m, dtype=torch.int32, device=dev)
+    val_c = torch.empty(m, dtype=torch.float32, device=dev)
+    y = torch.empty(n, dtype=torch.float32, device=dev)
+    # edge values follow their edges through the binning: bin (src, index) pairs
+    # would need a payload; the SpMV only needs some value per edge, so the
+    # binned list reuses val in its own order (same distribution)
+    t = {"bin": [], "reorder_relabel": [], "coo_to_csr": [], "spmv": []}
+    x2 = None
+    for _ in range(reps + 1):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        e[0].record()
+        boba.boba_bin_by_dst(src, dst, n, args.bin_bits, ws=ws_b, out=(sb, db))
+        e[1].record()
+        boba.boba_reorder_relabel(sb, db, n, with_order=False, ws=ws_rr, perm=perm, src_out=s2, dst_out=d2)
+        e[2].record()
+        boba.coo_to_csr(s2, d2, val, n, ws=ws_c, out=(rowptr, col, val_c))
+        e[3].record()
+        if x2 is None:
+            x2_h = np.empty(n, np.float32)
+            x2_h[perm.cpu().numpy()] = g.x
+            x2 = torch.from_numpy(x2_h).to(dev)
+        boba.spmv_csr(rowptr, col, val_c, x2, y=y, ws=ws_s)
+        e[4].record()
+        torch.cuda.synchronize()
+        for i, k in enumerate(t):
+            t[k].append(e[i].elapsed_time(e[i + 1]))
+    med = {k: float(np.median(v[1:])) for k, v in t.items()}
+    assert boba.boba_check_device_error() == boba.BOBA_OK
+    return {"bin_bits": args.bin_bits, "ms": med, "spmv_gflops": 2 * m / (med["spmv"] * 1e-3) / 1e9,
+            "spmv_speedup_vs_input_order": before_spmv_ms / med["spmv"]}
 
 
 def bench_batch(batch, reps, dev):

@@ -175,6 +175,23 @@ BOBA_API boba_status boba_batch_plan_launch(boba_batch_plan *plan, hipStream_t s
 BOBA_API boba_status boba_batch_plan_info(const boba_batch_plan *plan, int64_t *info4);
 BOBA_API boba_status boba_batch_plan_destroy(boba_batch_plan *plan);
 
+/* ------------------------------------------------ binning by destination ---
+ * A stable sort of the edges by dst >> shift, shift = max(0, bits(n - 1) -
+ * bin_bits): at most 2^bin_bits bins in order of destination, input order
+ * kept inside a bin.  Sec. 5.6 suggests binning (or sorting) an edge list that
+ * arrives in random order by destination before running BOBA.
+ *   src, dst          int32[m] input edges (IDs expected in [0, n); others are
+ *                     moved like any ID and reported by the next reorder)
+ *   bin_bits          1..31; >= bits(n - 1) gives a full stable sort by dst
+ *   src_out, dst_out  int32[m] output; must not alias the inputs
+ *   ws                at least boba_bin_by_dst_workspace(n, m) bytes, 256-byte aligned.
+ * Errors: ERR_ARG (NULL, aliasing, bin_bits), ERR_OVERFLOW (m or n >= 2^31),
+ * ERR_WORKSPACE. */
+BOBA_API size_t boba_bin_by_dst_workspace(int64_t n, int64_t m);
+BOBA_API boba_status boba_bin_by_dst(const int32_t *src, const int32_t *dst, int64_t m, int64_t n, int32_t bin_bits,
+                                     int32_t *src_out, int32_t *dst_out, void *ws, size_t ws_bytes,
+                                     hipStream_t stream);
+
 /* ------------------------------------------------------------ selector ---
  * A learned "will reordering pay off" selector (not in the paper; it targets
  * the net-speedup question of Sec. 1.1, Problem 2).

@@ -57,9 +57,11 @@ def lib():
         L.oracle_adam.argtypes = [P, P, P, P, I64, I64, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double]
         L.oracle_nbr.argtypes = [P, P, I64, I64, P, P]
+        L.oracle_bin_by_dst.argtypes = [P, P, I64, I64, ctypes.c_int, P, P]
         L.oracle_mlp_nparam.restype = I64
         for f in ("oracle_boba", "oracle_relabel", "oracle_coo_to_csr", "oracle_spmv64",
-                  "oracle_mlp_forward", "oracle_mlp_backward", "oracle_adam", "oracle_nbr"):
+                  "oracle_mlp_forward", "oracle_mlp_backward", "oracle_adam", "oracle_nbr",
+                  "oracle_bin_by_dst"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -107,6 +109,14 @@ def coo_to_csr(row, col, val, n_rows):
     _check(lib().oracle_coo_to_csr(_p(row), _p(col), _p(v), row.size, n_rows, _p(rowptr),
                                    _p(col_out), _p(val_out)), "coo_to_csr")
     return rowptr, col_out, val_out
+
+
+def bin_by_dst(src, dst, n, bin_bits):
+    """Edges stably sorted by dst >> shift (Sec. 5.6's binning by destination)."""
+    src, dst = _i32(src), _i32(dst)
+    so, do = np.empty_like(src), np.empty_like(dst)
+    _check(lib().oracle_bin_by_dst(_p(src), _p(dst), src.size, n, int(bin_bits), _p(so), _p(do)), "bin_by_dst")
+    return so, do
 
 
 def spmv64(rowptr, col, val, x, n_rows=None):

@@ -27,6 +27,9 @@
  *                    selector (not in the paper), FP64 forward, analytic
  *                    backward of the mean squared error, and one Adam step.
  *   oracle_nbr       the NBR spatial-locality metric of Sec. 5.2.
+ *   oracle_bin_by_dst  binning of the edge list by destination before BOBA,
+ *                    the remedy Sec. 5.6 suggests for edges in random order:
+ *                    a stable counting sort by dst >> shift.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -262,5 +265,33 @@ int oracle_nbr(const int32_t *rowptr, const int32_t *col, int64_t n, int64_t lin
     free(lines);
     *sum_ratio = s;
     *counted = c;
+    return ORACLE_OK;
+}
+
+/* Stable counting sort of the edges by bin = dst >> shift; the bins are the
+ * 2^bin_bits leading values of the bits(n - 1)-bit vertex IDs (shift =
+ * max(0, bits - bin_bits)).  Inside a bin the input order is kept. */
+int oracle_bin_by_dst(const int32_t *src, const int32_t *dst, int64_t m, int64_t n, int bin_bits,
+                      int32_t *src_out, int32_t *dst_out)
+{
+    if (m < 0 || n < 0 || bin_bits < 1) return ORACLE_ERR_ARG;
+    int bits = 0;
+    while (bits < 31 && ((int64_t)1 << bits) < n) ++bits;
+    const int key_bits = bin_bits < bits ? bin_bits : bits;
+    const int shift = bits - key_bits;
+    const int64_t nbins = (int64_t)1 << key_bits;
+    int64_t *start = (int64_t *)calloc((size_t)nbins + 1, sizeof(int64_t));
+    if (!start) return ORACLE_ERR_ARG;
+    for (int64_t k = 0; k < m; ++k) {
+        if (dst[k] < 0 || dst[k] >= n) { free(start); return ORACLE_ERR_RANGE; }
+        start[(dst[k] >> shift) + 1] += 1;                 /* bin sizes */
+    }
+    for (int64_t b = 0; b < nbins; ++b) start[b + 1] += start[b];   /* bin starts */
+    for (int64_t k = 0; k < m; ++k) {                      /* in input order: stable */
+        const int64_t at = start[dst[k] >> shift]++;
+        src_out[at] = src[k];
+        dst_out[at] = dst[k];
+    }
+    free(start);
     return ORACLE_OK;
 }

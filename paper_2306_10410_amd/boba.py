@@ -30,6 +30,8 @@ PROTOTYPES = {
     "boba_relabel": (_I32, [_P, _P, _I64, _P, _I64, _P, _P, _P]),
     "boba_reorder_relabel_workspace": (_SZ, [_I64, _I64]),
     "boba_reorder_relabel": (_I32, [_P, _P, _I64, _I64, _P, _P, _P, _P, _P, _SZ, _U32, _P]),
+    "boba_bin_by_dst_workspace": (_SZ, [_I64, _I64]),
+    "boba_bin_by_dst": (_I32, [_P, _P, _I64, _I64, _I32, _P, _P, _P, _SZ, _P]),
     "coo_to_csr_workspace": (_SZ, [_I64, _I64]),
     "coo_to_csr": (_I32, [_P, _P, _P, _I64, _I64, _P, _P, _P, _P, _SZ, _P]),
     "spmv_csr_workspace": (_SZ, [_I64, _I64]),
@@ -158,6 +160,24 @@ def boba_reorder_relabel(src, dst, n: int, *, with_order: bool = True, flags: in
     _check(load().boba_reorder_relabel(_ptr(src), _ptr(dst), m, n, _ptr(perm), _ptr(order) if with_order else None,
                                        _ptr(src_out), _ptr(dst_out), _ptr(ws), ws.numel(), flags, _stream(stream)))
     return perm, (order if with_order else None), src_out, dst_out
+
+
+def boba_bin_by_dst_workspace(n: int, m: int) -> int:
+    return int(load().boba_bin_by_dst_workspace(n, m))
+
+
+def boba_bin_by_dst(src, dst, n: int, bin_bits: int, *, ws=None, out=None, stream=None):
+    """Edges stably binned by destination (dst >> shift).  Returns (src_out, dst_out)."""
+    _dev_i32(src, "src")
+    _dev_i32(dst, "dst")
+    m = src.numel()
+    if dst.numel() != m:
+        raise ValueError("src and dst differ in length")
+    so, do = (torch.empty_like(src), torch.empty_like(dst)) if out is None else out
+    ws = _workspace(boba_bin_by_dst_workspace(n, m), src.device, ws)
+    _check(load().boba_bin_by_dst(_ptr(src), _ptr(dst), m, n, bin_bits, _ptr(so), _ptr(do), _ptr(ws), ws.numel(),
+                                  _stream(stream)))
+    return so, do
 
 
 def coo_to_csr_workspace(n_rows: int, m: int) -> int:

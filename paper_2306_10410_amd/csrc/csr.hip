@@ -421,3 +421,99 @@ extern "C" boba_status coo_to_csr(const int32_t *row, const int32_t *col, const 
     return device_scan<OpMax, true>("rowptr_scan", LoadArr{(const uint32_t *)rowptr}, StoreArr{(uint32_t *)rowptr}, nr + 1,
                                     L.partial, stream);
 }
+
+// ------------------------------------------------ binning by destination
+// A stable sort of the edges by dst >> shift: the remedy the paper suggests
+// for edge lists in random order (Sec. 5.6) -- bin (or sort) the COO by
+// destination before running BOBA.  shift = max(0, bits(n - 1) - bin_bits),
+// so the edges fall into at most 2^bin_bits bins in order of destination and
+// keep their input order inside a bin.  LSD radix passes of 8 bits over the
+// bin number, with the same kernels as coo_to_csr (key dst, payload src).
+namespace boba {
+namespace {
+
+struct BinLayout {
+    int32_t *keys_x, *vals_x;
+    uint32_t *hist, *partial, *colpart;
+    size_t bytes;
+    uint32_t tiles, colblocks;
+};
+
+BinLayout bin_layout(void *ws, int64_t m) {
+    BinLayout L;
+    L.tiles = ceil_div((uint64_t)m, kTile);
+    L.colblocks = ceil_div(L.tiles, kColTiles);
+    Carver c(ws);
+    L.keys_x = c.take<int32_t>((size_t)m);
+    L.vals_x = c.take<int32_t>((size_t)m);
+    L.hist = c.take<uint32_t>((size_t)L.tiles << kBits);
+    L.colpart = c.take<uint32_t>((size_t)L.colblocks << kBits);
+    L.partial = c.take<uint32_t>(scan_partials((uint64_t)L.colblocks << kBits));
+    L.bytes = c.bytes();
+    return L;
+}
+
+inline uint32_t id_bits(int64_t n) {
+    uint32_t bits = 0;
+    while (bits < 31 && (1ull << bits) < (uint64_t)n) ++bits;
+    return bits;
+}
+
+}  // namespace
+}  // namespace boba
+
+extern "C" size_t boba_bin_by_dst_workspace(int64_t n, int64_t m) {
+    if (n < 0 || m < 0) return 0;
+    return bin_layout(nullptr, m).bytes;
+}
+
+extern "C" boba_status boba_bin_by_dst(const int32_t *src, const int32_t *dst, int64_t m, int64_t n,
+                                       int32_t bin_bits, int32_t *src_out, int32_t *dst_out, void *ws,
+                                       size_t ws_bytes, hipStream_t stream) {
+    clear_error();
+    if (m < 0 || n < 0) return fail(BOBA_ERR_ARG, "boba_bin_by_dst: negative size");
+    if (m >= (1ll << 31) || n >= (1ll << 31))
+        return fail(BOBA_ERR_OVERFLOW, "boba_bin_by_dst: m and n must be < 2^31");
+    if (bin_bits < 1 || bin_bits > 31) return fail(BOBA_ERR_ARG, "boba_bin_by_dst: bin_bits must be in 1..31");
+    if (m == 0) return BOBA_OK;
+    if (!src || !dst || !src_out || !dst_out) return fail(BOBA_ERR_ARG, "boba_bin_by_dst: NULL pointer");
+    if (src_out == src || src_out == dst || dst_out == src || dst_out == dst)
+        return fail(BOBA_ERR_ARG, "boba_bin_by_dst: outputs may not alias the inputs");
+    const size_t need = boba_bin_by_dst_workspace(n, m);
+    if (!ws || ws_bytes < need || ((uintptr_t)ws & 255u))
+        return fail(BOBA_ERR_WORKSPACE, "boba_bin_by_dst: workspace needs %zu bytes, 256-byte aligned (got %zu at %p)",
+                    need, ws_bytes, ws);
+    const BinLayout L = bin_layout(ws, m);
+    const uint32_t um = (uint32_t)m;
+    const uint32_t total = id_bits(n);
+    const uint32_t key_bits = (uint32_t)bin_bits < total ? (uint32_t)bin_bits : total;
+    const uint32_t shift = total - key_bits;
+    const int passes = key_bits == 0 ? 0 : (int)((key_bits + kBits - 1) / kBits);
+    if (passes == 0) {  // a single bin: the edge list is unchanged
+        if (hipMemcpyAsync(src_out, src, (size_t)m * 4, hipMemcpyDeviceToDevice, stream) != hipSuccess ||
+            hipMemcpyAsync(dst_out, dst, (size_t)m * 4, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+            return fail(BOBA_ERR_HIP, "boba_bin_by_dst: copy failed");
+        return BOBA_OK;
+    }
+    const int32_t *kin = dst, *vin = src;
+    for (int p = 0; p < passes; ++p) {
+        const uint32_t sh = shift + (uint32_t)(p * kBits);
+        const bool to_out = ((passes - 1 - p) % 2) == 0;
+        int32_t *kout = to_out ? dst_out : L.keys_x;
+        int32_t *vout = to_out ? src_out : L.vals_x;
+        BOBA_LAUNCH("bin_hist", k_radix_hist<kBits>, dim3(L.tiles), dim3(kHistThreads), stream, kin, um, sh, L.tiles,
+                    L.hist);
+        BOBA_LAUNCH("bin_offsets", k_col_reduce<1 << kBits>, dim3(L.colblocks), dim3(1 << kBits), stream,
+                    (const uint32_t *)L.hist, L.tiles, L.colblocks, L.colpart);
+        if (boba_status e = device_scan<OpSum, false>("bin_offsets", LoadArr{L.colpart}, StoreArr{L.colpart},
+                                                      L.colblocks << kBits, L.partial, stream))
+            return e;
+        BOBA_LAUNCH("bin_offsets", k_col_down<1 << kBits>, dim3(L.colblocks), dim3(1 << kBits), stream, L.hist,
+                    L.tiles, L.colblocks, (const uint32_t *)L.colpart);
+        BOBA_LAUNCH("bin_scatter", (k_radix_scatter<kBits, false>), dim3(L.tiles), dim3(kBlock), stream, kin, vin,
+                    (const float *)nullptr, um, sh, L.tiles, (const uint32_t *)L.hist, kout, vout, (float *)nullptr);
+        kin = kout;
+        vin = vout;
+    }
+    return BOBA_OK;
+}

@@ -243,6 +243,49 @@ constexpr uint32_t kMaxBuckets = 1024;                          // LDS budget of
 constexpr uint32_t kSentinel = 0xFFFFFFFFu;
 constexpr int kMinThreads = 1024;
 constexpr int kMinGroup = 16;                                   // segments in flight per wave
+constexpr uint32_t kLongMax = 512;                              // long segments a workgroup can queue
+constexpr uint32_t kChunk = 16 * kWave;                         // records per wave step, 8 loads of 2 per lane
+constexpr uint32_t kInlineMax = 2 * kChunk;                     // longer segment rests go to the queue
+
+// Queue of segment rests longer than kInlineMax records: an entry is {tile,
+// first record, end, first chunk}; one 64-bit LDS atomic hands out the slot
+// (high word) and the chunks (low word) together, so chunk bases grow with
+// the slot and a wave can walk the entries in order.
+struct LongQueue {
+    uint32_t e[kLongMax][4];
+    unsigned long long top;
+};
+
+// Pushes the rest [k1, e1) of tile's segment; false when the queue is full
+// (the caller then works through it itself).  Wave-uniform arguments.
+__device__ inline bool long_push(LongQueue &q, uint32_t tile, uint32_t k1, uint32_t e1, uint32_t lane) {
+    unsigned long long t = 0;
+    if (lane == 0) t = atomicAdd(&q.top, (1ull << 32) | ((e1 - k1 + kChunk - 1) / kChunk));
+    t = __shfl(t, 0, kWave);
+    const uint32_t slot = (uint32_t)(t >> 32);
+    if (slot >= kLongMax) return false;
+    if (lane == 0) {
+        q.e[slot][0] = tile;
+        q.e[slot][1] = k1;
+        q.e[slot][2] = e1;
+        q.e[slot][3] = (uint32_t)t;
+    }
+    return true;
+}
+
+// Calls f(tile, first record, end) for every chunk of the queued rests,
+// chunks dealt round-robin over the waves.  After a barrier.
+template <class F>
+__device__ inline void long_drain(const LongQueue &q, uint32_t wave, uint32_t nwave, F &&f) {
+    const uint32_t nq = min((uint32_t)(q.top >> 32), kLongMax);
+    if (nq == 0) return;
+    const uint32_t units = q.e[nq - 1][3] + (q.e[nq - 1][2] - q.e[nq - 1][1] + kChunk - 1) / kChunk;
+    uint32_t i = 0;
+    for (uint32_t u = wave; u < units; u += nwave) {
+        while (i + 1 < nq && q.e[i + 1][3] <= u) ++i;
+        f(q.e[i][0], q.e[i][1] + (u - q.e[i][3]) * kChunk, q.e[i][2]);
+    }
+}
 
 inline uint32_t split_region(uint32_t nb) { return (kTileT + 3 * nb + 3) & ~3u; }
 
@@ -294,19 +337,38 @@ __global__ __launch_bounds__(kSplitThreads) void k_bucket_split(const int32_t *_
         const uint32_t k0 = (t - (h ? tiles_half : 0u)) * kTileT;
         for (uint32_t i = tid; i < nb; i += kSplitThreads) hist[i] = 0;
         __syncthreads();
+        // A wave's 256 consecutive elements of one step j often share a
+        // bucket when the input is sorted (a bucket spans 32768 IDs); then one
+        // atomic counts them all instead of 256 same-address LDS atomics.
+        const uint32_t lane = tid & (kWave - 1);
+        bool same[kSplitPer / 4];
 #pragma unroll
         for (int j = 0; j < kSplitPer / 4; ++j) {
+            bool all_ok = true;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const uint32_t e = k0 + j * (4 * kSplitThreads) + 4 * tid + q;
                 const int32_t x = v[4 * j + q];
-                if (e < m) {
-                    if ((uint32_t)x < n) {
+                const bool ok = e < m && (uint32_t)x < n;
+                if (e < m && !ok) {
+                    bad = true;
+                    v[4 * j + q] = -1;
+                }
+                all_ok = all_ok && ok;
+            }
+            const uint32_t b0 = (uint32_t)__shfl(v[4 * j], 0, kWave) >> kVBits;
+            const bool mine = all_ok && ((uint32_t)v[4 * j] >> kVBits) == b0 &&
+                              ((uint32_t)v[4 * j + 1] >> kVBits) == b0 && ((uint32_t)v[4 * j + 2] >> kVBits) == b0 &&
+                              ((uint32_t)v[4 * j + 3] >> kVBits) == b0;
+            same[j] = __ballot(mine) == ~0ull;
+            if (same[j]) {
+                if (lane == 0) atomicAdd(&hist[b0], 4u * kWave);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int32_t x = v[4 * j + q];
+                    if (x >= 0 && k0 + j * (4 * kSplitThreads) + 4 * tid + q < m)
                         atomicAdd(&hist[(uint32_t)x >> kVBits], 1u);
-                    } else {
-                        bad = true;
-                        v[4 * j + q] = -1;
-                    }
                 }
             }
         }
@@ -327,13 +389,24 @@ __global__ __launch_bounds__(kSplitThreads) void k_bucket_split(const int32_t *_
 
 #pragma unroll
         for (int j = 0; j < kSplitPer / 4; ++j) {
+            if (same[j]) {  // one bucket: 256 slots in element order
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(&cur[(uint32_t)v[4 * j] >> kVBits], 4u * kWave);
+                base = __shfl(base, 0, kWave) + 4 * lane;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int32_t x = v[4 * j + q];
-                if (x >= 0) {
+                for (int q = 0; q < 4; ++q) {
                     const uint32_t o = j * (4 * kSplitThreads) + 4 * tid + q;
-                    const uint32_t slot = atomicAdd(&cur[(uint32_t)x >> kVBits], 1u);
-                    stage[slot] = (o << kVBits) | ((uint32_t)x & (kBucketW - 1));
+                    stage[base + q] = (o << kVBits) | ((uint32_t)v[4 * j + q] & (kBucketW - 1));
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int32_t x = v[4 * j + q];
+                    if (x >= 0) {
+                        const uint32_t o = j * (4 * kSplitThreads) + 4 * tid + q;
+                        const uint32_t slot = atomicAdd(&cur[(uint32_t)x >> kVBits], 1u);
+                        stage[slot] = (o << kVBits) | ((uint32_t)x & (kBucketW - 1));
+                    }
                 }
             }
         }
@@ -373,11 +446,13 @@ __global__ __launch_bounds__(kMinThreads) void k_bucket_min(const uint32_t *__re
                                                             uint32_t hbase1, uint32_t stride,
                                                             uint32_t *__restrict__ out) {
     __shared__ uint32_t lr[kBucketW];
+    __shared__ LongQueue longq;
     const uint32_t b = blockIdx.x % nb;
     const uint32_t s = blockIdx.x / nb;
     const uint32_t t0 = s * tps;
     const uint32_t t1 = min(nt, t0 + tps);
     for (uint32_t i = threadIdx.x; i < kBucketW; i += kMinThreads) lr[i] = kInf;
+    if (threadIdx.x == 0) longq.top = 0;
     __syncthreads();
 
     const uint32_t lane = threadIdx.x & (kWave - 1);
@@ -393,6 +468,23 @@ __global__ __launch_bounds__(kMinThreads) void k_bucket_min(const uint32_t *__re
         const uint32_t p = pb + stride * (rec >> kVBits);
         if (p < lr[i]) atomicMin(&lr[i], p);
     };
+    // records [kb, min(kb + kChunk, e1)) of a tile's segment, 8 loads in
+    // flight per lane
+    auto fold_chunk = [&](uint32_t tile, uint32_t kb, uint32_t e1) {
+        const bool h = tile >= tiles_half;
+        const uint32_t pb = (h ? hbase1 : 0u) + stride * ((tile - (h ? tiles_half : 0u)) * kTileT);
+        uint2 xs[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t k = kb + 2 * (u * kWave + lane);
+            xs[u] = k < e1 ? *(const uint2 *)(recs + (size_t)tile * region + k) : make_uint2(kSentinel, kSentinel);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            fold(xs[u].x, pb);
+            fold(xs[u].y, pb);
+        }
+    };
     const uint32_t *beg = off_t + (size_t)b * nt;
     const uint32_t *end = off_t + (size_t)(b + 1) * nt;
     // A wave takes `batch` (<= 64) tiles at a time: one coalesced load of
@@ -403,6 +495,7 @@ __global__ __launch_bounds__(kMinThreads) void k_bucket_min(const uint32_t *__re
         const uint32_t my = tb + lane;
         const uint32_t sb = lane < cnt ? beg[my] : 0u;
         const uint32_t se = lane < cnt ? end[my] : 0u;
+        const uint64_t longs = __ballot(se - sb > 2 * kWave);  // segments past one load per lane
         uint2 cur[kMinGroup], nxt[kMinGroup];
         auto load_group = [&](uint32_t g0, uint2 (&dst)[kMinGroup]) {
 #pragma unroll
@@ -427,20 +520,23 @@ __global__ __launch_bounds__(kMinThreads) void k_bucket_min(const uint32_t *__re
                 uint2 x = cur[g];
                 fold(x.x, pb);
                 fold(x.y, pb);
-                // segments longer than 128 records (rare): finish them here
-                const uint32_t e0 = __shfl(se, gi & (kWave - 1), kWave);
-                uint32_t k = __shfl(sb, gi & (kWave - 1), kWave) + 2 * lane + 2 * kWave;
-                while (gi < cnt && k < e0) {
-                    x = *(const uint2 *)(recs + (size_t)tile * region + k);
-                    fold(x.x, pb);
-                    fold(x.y, pb);
-                    k += 2 * kWave;
-                }
+            }
+            // the rest of a segment longer than 128 records: folded here up
+            // to kInlineMax records, queued beyond (a sorted input makes whole
+            // tiles one segment) and shared out over all waves at the end
+            for (uint64_t mk = (longs >> g0) & ((1ull << kMinGroup) - 1); mk; mk &= mk - 1) {
+                const uint32_t gi = g0 + (uint32_t)__builtin_ctzll(mk);
+                const uint32_t e0 = __shfl(se, gi, kWave);
+                const uint32_t k1 = __shfl(sb, gi, kWave) + 2 * kWave;
+                if (e0 - k1 <= kInlineMax || !long_push(longq, tb + gi, k1, e0, lane))
+                    for (uint32_t kb = k1; kb < e0; kb += kChunk) fold_chunk(tb + gi, kb, e0);
             }
 #pragma unroll
             for (int g = 0; g < kMinGroup; ++g) cur[g] = nxt[g];
         }
     }
+    __syncthreads();
+    long_drain(longq, wave, NWAVE, fold_chunk);
     __syncthreads();
     uint32_t *o = out + (size_t)s * n + (size_t)b * kBucketW;
     const uint32_t cnt = min(kBucketW, n - b * kBucketW);
@@ -463,6 +559,7 @@ __global__ __launch_bounds__(kMinThreads) void k_bucket_relabel(const uint32_t *
                                                                 const int32_t *__restrict__ perm,
                                                                 uint32_t *__restrict__ vals) {
     __shared__ uint32_t lp[kBucketW];
+    __shared__ LongQueue longq;
     const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);  // neighbouring buckets share lines
     const uint32_t b = w % nb;
     const uint32_t s = w / nb;
@@ -470,10 +567,30 @@ __global__ __launch_bounds__(kMinThreads) void k_bucket_relabel(const uint32_t *
     const uint32_t t1 = min(nt, t0 + tps);
     const uint32_t cntv = min(kBucketW, n - b * kBucketW);
     for (uint32_t i = threadIdx.x; i < cntv; i += kMinThreads) lp[i] = (uint32_t)perm[(size_t)b * kBucketW + i];
+    if (threadIdx.x == 0) longq.top = 0;
     __syncthreads();
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = threadIdx.x / kWave;
     constexpr uint32_t NWAVE = kMinThreads / kWave;
+    // new IDs of records [kb, min(kb + kChunk, e1)) of a tile's segment, 8
+    // loads in flight per lane
+    auto relabel_chunk = [&](uint32_t tile, uint32_t kb, uint32_t e1) {
+        uint2 xs[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t kk = kb + 2 * (u * kWave + lane);
+            xs[u] = kk < e1 ? *(const uint2 *)(recs + (size_t)tile * region + kk) : make_uint2(kSentinel, kSentinel);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t kk = kb + 2 * (u * kWave + lane);
+            if (kk >= e1) continue;
+            uint2 v;
+            v.x = xs[u].x != kSentinel ? lp[xs[u].x & (kBucketW - 1)] : kSentinel;
+            v.y = xs[u].y != kSentinel ? lp[xs[u].y & (kBucketW - 1)] : kSentinel;
+            *(uint2 *)(vals + (size_t)tile * region + kk) = v;
+        }
+    };
     const uint32_t *beg = off_t + (size_t)b * nt;
     const uint32_t *end = off_t + (size_t)(b + 1) * nt;
     // same batching and software pipelining as bucket_min
@@ -481,6 +598,7 @@ __global__ __launch_bounds__(kMinThreads) void k_bucket_relabel(const uint32_t *
         const uint32_t cnt = min(batch, t1 - tb);
         const uint32_t sb = lane < cnt ? beg[tb + lane] : 0u;
         const uint32_t se = lane < cnt ? end[tb + lane] : 0u;
+        const uint64_t longs = __ballot(se - sb > 2 * kWave);
         uint2 cur[kMinGroup], nxt[kMinGroup];
         auto load_group = [&](uint32_t g0, uint2 (&dst)[kMinGroup]) {
 #pragma unroll
@@ -502,22 +620,29 @@ __global__ __launch_bounds__(kMinThreads) void k_bucket_relabel(const uint32_t *
                 const uint32_t tile = tb + gi;
                 const uint32_t e0 = __shfl(se, gi & (kWave - 1), kWave);
                 uint32_t k = __shfl(sb, gi & (kWave - 1), kWave) + 2 * lane;
-                uint2 r2 = cur[g];
-                // segments longer than 128 records (rare) loop here
-                while (gi < cnt && k < e0) {
+                const uint2 r2 = cur[g];
+                if (gi < cnt && k < e0) {
                     uint2 v;
                     v.x = r2.x != kSentinel ? lp[r2.x & (kBucketW - 1)] : kSentinel;
                     v.y = r2.y != kSentinel ? lp[r2.y & (kBucketW - 1)] : kSentinel;
                     *(uint2 *)(vals + (size_t)tile * region + k) = v;
-                    k += 2 * kWave;
-                    if (k >= e0) break;
-                    r2 = *(const uint2 *)(recs + (size_t)tile * region + k);
                 }
+            }
+            // the rest of a segment longer than 128 records, as in
+            // bucket_min: here up to kInlineMax records, else queued
+            for (uint64_t mk = (longs >> g0) & ((1ull << kMinGroup) - 1); mk; mk &= mk - 1) {
+                const uint32_t gi = g0 + (uint32_t)__builtin_ctzll(mk);
+                const uint32_t e0 = __shfl(se, gi, kWave);
+                const uint32_t k1 = __shfl(sb, gi, kWave) + 2 * kWave;
+                if (e0 - k1 <= kInlineMax || !long_push(longq, tb + gi, k1, e0, lane))
+                    for (uint32_t kb = k1; kb < e0; kb += kChunk) relabel_chunk(tb + gi, kb, e0);
             }
 #pragma unroll
             for (int g = 0; g < kMinGroup; ++g) cur[g] = nxt[g];
         }
     }
+    __syncthreads();
+    long_drain(longq, wave, NWAVE, relabel_chunk);
 }
 
 __global__ __launch_bounds__(kSplitThreads) void k_tile_unsplit(const uint32_t *__restrict__ recs,

@@ -118,6 +118,20 @@ def test_relabel_csr_spmv_argument_errors(lib):
     assert lib.boba_check_device_error(None, None) == boba.BOBA_ERR_ARG
 
 
+def test_bin_by_dst_argument_errors(lib):
+    need = lib.boba_bin_by_dst_workspace(5, 3)
+    A, B, C, D = FAKE, P(0x10100), P(0x10200), P(0x10300)
+    assert lib.boba_bin_by_dst(A, B, 3, 5, 0, C, D, A, need, None) == boba.BOBA_ERR_ARG      # bin_bits
+    assert lib.boba_bin_by_dst(A, B, 3, 5, 32, C, D, A, need, None) == boba.BOBA_ERR_ARG
+    assert lib.boba_bin_by_dst(A, B, -3, 5, 4, C, D, A, need, None) == boba.BOBA_ERR_ARG
+    assert lib.boba_bin_by_dst(A, B, 1 << 31, 5, 4, C, D, A, need, None) == boba.BOBA_ERR_OVERFLOW
+    assert lib.boba_bin_by_dst(A, None, 3, 5, 4, C, D, A, need, None) == boba.BOBA_ERR_ARG
+    assert lib.boba_bin_by_dst(A, B, 3, 5, 4, A, D, A, need, None) == boba.BOBA_ERR_ARG      # aliasing
+    assert lib.boba_bin_by_dst(A, B, 3, 5, 4, C, B, A, need, None) == boba.BOBA_ERR_ARG
+    assert lib.boba_bin_by_dst(A, B, 3, 5, 4, C, D, A, need - 1, None) == boba.BOBA_ERR_WORKSPACE
+    assert lib.boba_bin_by_dst(None, None, 0, 0, 4, None, None, None, 0, None) == boba.BOBA_OK
+
+
 def test_binding_refuses_host_tensors():
     import torch
     x = torch.zeros(4, dtype=torch.int32)

@@ -288,3 +288,45 @@ def test_mostly_isolated_and_hub_graphs():
         perm, order = boba.boba_reorder(dev(s), dev(d), n)
         p_ref, o_ref = oracle.boba(s, d, n)
         assert np.array_equal(host(perm), p_ref) and np.array_equal(host(order), o_ref)
+
+
+@pytest.mark.parametrize("n,m", [(1, 7), (5, 4097), (1000, 8191), (70001, 300007), ((1 << 20) + 3, 1 << 22)])
+def test_bin_by_dst_matches_oracle(n, m):
+    src, dst = graphgen.uniform_edges(n, m, 92 + n % 89)
+    s, d = dev(src), dev(dst)
+    for bb in (1, 4, 8, 12, 16, 31):
+        so, do = boba.boba_bin_by_dst(s, d, n, bb)
+        so_ref, do_ref = oracle.bin_by_dst(src, dst, n, bb)
+        assert np.array_equal(host(so), so_ref) and np.array_equal(host(do), do_ref), bb
+
+
+def test_bin_then_reorder_restores_a_shuffled_grid():
+    # Sec. 5.6: a mesh whose edges arrive in random order; binning by
+    # destination first, then BOBA, must match the oracle on the binned list
+    s, d = graphgen.grid(300, 300)
+    g = graphgen.Graph("grid", 90000, s, d)
+    src, dst = graphgen.shuffle_edges(g.src, g.dst, 93)
+    so, do = boba.boba_bin_by_dst(dev(src), dev(dst), g.n, 8)
+    so_ref, do_ref = oracle.bin_by_dst(src, dst, g.n, 8)
+    assert np.array_equal(host(so), so_ref) and np.array_equal(host(do), do_ref)
+    perm, order = boba.boba_reorder(so, do, g.n)
+    p_ref, o_ref = oracle.boba(so_ref, do_ref, g.n)
+    assert np.array_equal(host(perm), p_ref) and np.array_equal(host(order), o_ref)
+
+
+@pytest.mark.parametrize("case", ["dst_sorted", "one_hot_bucket"])
+def test_sorted_inputs_long_segments(case):
+    # A destination-sorted list makes each destination tile one or two long
+    # runs of a single vertex bucket.  With every destination in one bucket
+    # (2^25 vertices: one slice) a single workgroup meets 1024 such runs, more
+    # than it can queue, so the inline fallback runs as well.
+    rng = np.random.default_rng(94)
+    if case == "dst_sorted":
+        n, m = (1 << 20) + 3, (1 << 23) + 5
+        dst = np.sort(rng.integers(0, n, m)).astype(np.int32)
+    else:
+        n, m = 1 << 25, (1 << 25) + 7
+        dst = np.sort(rng.integers(0, 1 << 15, m)).astype(np.int32)
+    src = rng.integers(0, n, m).astype(np.int32)
+    g = graphgen.Graph(case, n, src, dst)
+    full_path_check(g, boba, interleaved=case == "dst_sorted", check_spmv=False)

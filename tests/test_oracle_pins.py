@@ -346,3 +346,27 @@ def test_nbr_closed_forms():
     over_n, over_nonempty = oracle.nbr(rowptr, col, 3)
     assert math.isclose(over_nonempty, (0.25 + 1.0) / 2)
     assert math.isclose(over_n, (0.25 + 1.0) / 3)
+
+
+def test_bin_by_dst_pins():
+    rng = np.random.default_rng(31)
+    for n, m in [(1, 5), (2, 9), (37, 200), (1000, 5000), (1 << 12, 1 << 14)]:
+        src = rng.integers(0, n, m).astype(np.int32)
+        dst = rng.integers(0, n, m).astype(np.int32)
+        bits = int(np.ceil(np.log2(n))) if n > 1 else 0
+        for bb in (1, 3, 8, 16, 31):
+            so, do = oracle.bin_by_dst(src, dst, n, bb)
+            shift = max(0, bits - bb)
+            order = np.argsort(dst >> shift, kind="stable")  # a library routine, not the oracle's counting sort
+            assert np.array_equal(so, src[order]) and np.array_equal(do, dst[order]), (n, m, bb)
+            assert np.all(np.diff(do >> shift) >= 0)
+        # enough bins: a full stable sort by destination
+        so, do = oracle.bin_by_dst(src, dst, n, 31)
+        assert np.array_equal(do, np.sort(dst)) and sorted(zip(so, do)) == sorted(zip(src, dst))
+    # one bit, worked by hand: n = 4 (2-bit IDs), bins {0,1} | {2,3}, input order kept inside
+    src = np.array([10, 11, 12, 13, 14], np.int32)
+    dst = np.array([3, 0, 2, 1, 0], np.int32)
+    so, do = oracle.bin_by_dst(src, dst, 4, 1)
+    assert list(do) == [0, 1, 0, 3, 2] and list(so) == [11, 13, 14, 10, 12]
+    with pytest.raises(Exception):
+        oracle.bin_by_dst(src, np.array([0, 1, 2, 3, 4], np.int32), 4, 2)  # out of range
