@@ -43,6 +43,8 @@ PAPER_CONTEXT = {
                      "hardware": "NVIDIA V100 32 GB", "source": "Sec. 1.2 (timing), Sec. 5.1 (hardware)"},
     "spmv_speedup_boba_vs_random": {"median": 3.5, "range": [1.17, 6.25], "workloads": "skewed datasets of Table 2",
                                     "hardware": "NVIDIA V100 32 GB", "source": "Sec. 5.1"},
+    "nbr": {"kron_g500-logn20": {"random": 0.75, "boba": 0.74}, "kron_g500-logn21": {"random": 0.72, "boba": 0.72},
+            "delaunay_n24": {"random": 0.99, "boba": 0.48}, "source": "Table 1 (NBR over CSR rows, Sec. 5.2)"},
 }
 
 
@@ -299,6 +301,21 @@ def main():
     spmv_agree = float(np.linalg.norm(ya - yb) / max(np.linalg.norm(yb), 1e-30))
     assert boba.boba_check_device_error() == boba.BOBA_OK
 
+    # locality of the CSR rows (NBR of Sec. 5.2, 32-ID lines) before and after
+    ws_nbr = torch.empty(boba.boba_nbr_workspace(n, m), dtype=torch.uint8, device=dev)
+    nbr_before = boba.boba_nbr(rp0, col0, n, 32, ws=ws_nbr)
+    en = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    en[0].record()
+    nbr_after = boba.boba_nbr(rowptr, col, n, 32, ws=ws_nbr)  # waits for its result
+    en[1].record()
+    torch.cuda.synchronize()
+    nbr = {"line_ids": 32, "ms": en[0].elapsed_time(en[1]),
+           "before": {"over_all_rows": nbr_before[0], "over_nonempty_rows": nbr_before[1]},
+           "after": {"over_all_rows": nbr_after[0], "over_nonempty_rows": nbr_after[1]}}
+    log(f"NBR before {nbr_before[1]:.4f} after {nbr_after[1]:.4f} (non-empty rows), {nbr['ms']:.2f} ms")
+    del ws_nbr
+    assert boba.boba_check_device_error() == boba.BOBA_OK
+
     binned = None
     if args.bin_bits > 0:
         binned = bench_binned(args, g, src, dst, val, x, dev, ws_rr, ws_c, ws_s, before_spmv_ms)
@@ -364,6 +381,7 @@ def main():
         "cpu_baseline": cpu,
         "batched": batched,
         "binned": binned,
+        "nbr": nbr,
         "paper_context": PAPER_CONTEXT,
         "device": torch.cuda.get_device_name(0),
         "source_digest": source_digest(),

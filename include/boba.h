@@ -192,6 +192,32 @@ BOBA_API boba_status boba_bin_by_dst(const int32_t *src, const int32_t *dst, int
                                      int32_t *src_out, int32_t *dst_out, void *ws, size_t ws_bytes,
                                      hipStream_t stream);
 
+/* ----------------------------------------------------------------- NBR ---
+ * The spatial-locality metric of Sec. 5.2 over the rows of a CSR matrix: for
+ * every row v with a non-empty neighbourhood N(v) (its column IDs, duplicates
+ * included), the number of distinct cache lines the IDs fall in divided by
+ * |N(v)|, where a line holds line_ids consecutive IDs (ID c lies in line
+ * c / line_ids).  NBR is the mean of that ratio; lower is more local.
+ *   rowptr         int32[n_rows + 1], col int32[nnz] (NULL when nnz = 0),
+ *                  rowptr as for spmv_csr (clamped, never read out of bounds).
+ *   line_ids       a power of two in [1, 2^30] (32: 128-byte lines of 4-byte values).
+ *   lines_per_row  int32[n_rows] output, distinct lines per row (0 for empty
+ *                  rows), or NULL.
+ *   result         device double[2] output: result[0] = sum of the ratios over
+ *                  the non-empty rows, result[1] = how many rows that is, so
+ *                  NBR over all rows = result[0] / n_rows and over non-empty
+ *                  rows = result[0] / result[1].  The sum is taken in a fixed
+ *                  order (bit-reproducible).
+ *   ws             at least boba_nbr_workspace(n_rows, nnz) bytes, 256-byte aligned.
+ * Column IDs outside [0, n_cols) are skipped and flagged
+ * (boba_check_device_error).
+ * Errors: ERR_ARG (NULL, line_ids), ERR_OVERFLOW (a size >= 2^31),
+ * ERR_WORKSPACE, ERR_HIP. */
+BOBA_API size_t boba_nbr_workspace(int64_t n_rows, int64_t nnz);
+BOBA_API boba_status boba_nbr(const int32_t *rowptr, const int32_t *col, int64_t n_rows, int64_t n_cols,
+                              int64_t nnz, int32_t line_ids, int32_t *lines_per_row, double *result, void *ws,
+                              size_t ws_bytes, hipStream_t stream);
+
 /* ------------------------------------------------------------ selector ---
  * A learned "will reordering pay off" selector (not in the paper; it targets
  * the net-speedup question of Sec. 1.1, Problem 2).

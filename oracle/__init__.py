@@ -56,7 +56,7 @@ def lib():
         L.oracle_mlp_backward.argtypes = [P, P, P, I64, P, P]
         L.oracle_adam.argtypes = [P, P, P, P, I64, I64, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double]
-        L.oracle_nbr.argtypes = [P, P, I64, I64, P, P]
+        L.oracle_nbr.argtypes = [P, P, I64, I64, P, P, P]
         L.oracle_bin_by_dst.argtypes = [P, P, I64, I64, ctypes.c_int, P, P]
         L.oracle_mlp_nparam.restype = I64
         for f in ("oracle_boba", "oracle_relabel", "oracle_coo_to_csr", "oracle_spmv64",
@@ -158,11 +158,14 @@ def adam(params, m1, m2, grad, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
                              lr, b1, b2, eps), "adam")
 
 
-def nbr(rowptr, col, n, line_ids=32):
+def nbr(rowptr, col, n, line_ids=32, per_row=False):
     """NBR (Sec. 5.2) over CSR rows.  Returns (mean over all n, mean over
-    vertices with a non-empty neighbourhood)."""
+    vertices with a non-empty neighbourhood), and with per_row also the
+    distinct lines of every row."""
     rowptr, col = _i32(rowptr), _i32(col)
     s = np.zeros(1, np.float64)
     c = np.zeros(1, np.int64)
-    _check(lib().oracle_nbr(_p(rowptr), _p(col), n, line_ids, _p(s), _p(c)), "nbr")
-    return (s[0] / n if n else 0.0), (s[0] / c[0] if c[0] else 0.0)
+    d = np.zeros(n, np.int32) if per_row else None
+    _check(lib().oracle_nbr(_p(rowptr), _p(col), n, line_ids, _p(s), _p(c), _p(d) if per_row else None), "nbr")
+    means = (s[0] / n if n else 0.0), (s[0] / c[0] if c[0] else 0.0)
+    return (*means, d) if per_row else means

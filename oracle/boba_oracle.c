@@ -231,7 +231,8 @@ int oracle_adam(double *params, double *m1, double *m2, const double *grad, int6
 /* NBR (Sec. 5.2): (1/n) sum over vertices with a non-empty neighbourhood of
  * (#distinct cache lines spanned by N(v)) / |N(v)|, a line holding `line_ids`
  * consecutive IDs.  Neighbourhoods are CSR rows; duplicates count in |N(v)|
- * as they occur.  Returns the sum and the number of vertices counted. */
+ * as they occur.  Returns the sum and the number of vertices counted, and
+ * when `distinct` is not NULL the distinct lines of every row (0 if empty). */
 static int cmp_i64(const void *a, const void *b)
 {
     int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
@@ -239,7 +240,7 @@ static int cmp_i64(const void *a, const void *b)
 }
 
 int oracle_nbr(const int32_t *rowptr, const int32_t *col, int64_t n, int64_t line_ids,
-               double *sum_ratio, int64_t *counted)
+               double *sum_ratio, int64_t *counted, int32_t *distinct)
 {
     if (line_ids <= 0) return ORACLE_ERR_ARG;
     double s = 0.0;
@@ -248,6 +249,7 @@ int oracle_nbr(const int32_t *rowptr, const int32_t *col, int64_t n, int64_t lin
     int64_t *lines = NULL;
     for (int64_t v = 0; v < n; ++v) {
         int64_t deg = rowptr[v + 1] - rowptr[v];
+        if (distinct) distinct[v] = 0;
         if (deg == 0) continue;
         if (deg > cap) {
             free(lines);
@@ -259,6 +261,7 @@ int oracle_nbr(const int32_t *rowptr, const int32_t *col, int64_t n, int64_t lin
         qsort(lines, (size_t)deg, sizeof(int64_t), cmp_i64);
         int64_t nd = 1;
         for (int64_t e = 1; e < deg; ++e) nd += lines[e] != lines[e - 1];
+        if (distinct) distinct[v] = (int32_t)nd;
         s += (double)nd / (double)deg;
         c += 1;
     }

@@ -36,6 +36,8 @@ PROTOTYPES = {
     "coo_to_csr": (_I32, [_P, _P, _P, _I64, _I64, _P, _P, _P, _P, _SZ, _P]),
     "spmv_csr_workspace": (_SZ, [_I64, _I64]),
     "spmv_csr": (_I32, [_P, _P, _P, _I64, _I64, _I64, _P, _P, _P, _SZ, _P]),
+    "boba_nbr_workspace": (_SZ, [_I64, _I64]),
+    "boba_nbr": (_I32, [_P, _P, _I64, _I64, _I64, _I32, _P, _P, _P, _SZ, _P]),
     "boba_batch_workspace": (_SZ, [_I32, _P, _P, _P]),
     "boba_batch_plan_create": (_I32, [_I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P, _P, _P]),
     "boba_batch_plan_launch": (_I32, [_P, _P]),
@@ -215,6 +217,30 @@ def spmv_csr(rowptr, col, val, x, *, y=None, ws=None, stream=None):
     _check(load().spmv_csr(_ptr(rowptr), _ptr(col), _ptr(val), n_rows, x.numel(), col.numel(), _ptr(x), _ptr(y),
                            _ptr(ws), ws.numel(), _stream(stream)))
     return y
+
+
+def boba_nbr_workspace(n_rows: int, nnz: int) -> int:
+    return int(load().boba_nbr_workspace(n_rows, nnz))
+
+
+def boba_nbr(rowptr, col, n_cols: int, line_ids: int = 32, *, per_row=False, ws=None, stream=None):
+    """NBR of the CSR rows (Sec. 5.2).  Returns (mean over all rows, mean over
+    non-empty rows), plus the distinct lines per row when per_row is set.
+    Waits for the stream (the two means come back to the host)."""
+    _dev_i32(rowptr, "rowptr")
+    _dev_i32(col, "col")
+    n_rows = rowptr.numel() - 1
+    dev = rowptr.device
+    lines = torch.empty(max(n_rows, 0), dtype=torch.int32, device=dev) if per_row else None
+    result = torch.empty(2, dtype=torch.float64, device=dev)
+    ws = _workspace(boba_nbr_workspace(n_rows, col.numel()), dev, ws)
+    _check(load().boba_nbr(_ptr(rowptr), _ptr(col), n_rows, n_cols, col.numel(), line_ids, _ptr(lines),
+                           _ptr(result), _ptr(ws), ws.numel(), _stream(stream)))
+    if stream is not None:
+        stream.synchronize()
+    total, counted = result.tolist()
+    means = (total / n_rows if n_rows else 0.0, total / counted if counted else 0.0)
+    return (*means, lines) if per_row else means
 
 
 def boba_check_device_error(stream=None) -> int:

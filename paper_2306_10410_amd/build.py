@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libboba.so")
 
-SOURCES = ["common.hip", "timing.hip", "reorder.hip", "csr.hip", "spmv.hip", "batch.hip", "select.hip"]
+SOURCES = ["common.hip", "timing.hip", "reorder.hip", "csr.hip", "spmv.hip", "nbr.hip", "batch.hip", "select.hip"]
 
 ARCH = "gfx950"
 HIPCC_FLAGS = [

@@ -1,0 +1,293 @@
+// NBR spatial-locality metric over CSR rows (Sec. 5.2): for every row v with
+// a non-empty neighbourhood N(v), the number of distinct cache lines its
+// column IDs fall in (a line holds line_ids consecutive IDs) divided by
+// |N(v)|, duplicates counted in |N(v)| as they occur; the metric is the mean
+// of that ratio.
+//   split   the first row of every chunk of kChunkE entries (a row belongs to
+//           the chunk its first entry falls in)
+//   chunk   a workgroup per chunk stages the line IDs of its rows' entries in
+//           LDS; a wavefront per row counts the entries whose line no earlier
+//           entry of the row has (one broadcast LDS read per earlier entry).
+//           Rows longer than kSmall are put on a list.
+//   big     a workgroup per listed row: an LDS bitmap over up to 2^20 lines,
+//           one pass per 2^20 lines of the row's [min, max] line span; an
+//           entry is new when its bit was clear.
+//   reduce  the per-row ratios summed in a fixed order (per part of the rows,
+//           then over the parts), so the result is bit-reproducible.
+#include "internal.h"
+
+namespace boba {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr uint32_t kChunkE = 2048;                // entries per chunk
+constexpr uint32_t kSmall = 256;                  // longest row a wavefront counts
+constexpr uint32_t kWin = kChunkE + kSmall;       // entries a chunk stages
+constexpr int kBigThreads = 1024;
+constexpr uint32_t kBitmapWords = 32768;          // 128 KB: 2^20 lines per pass
+constexpr uint32_t kParts = 1024;                 // parts of the rows in the reduction
+
+__device__ __forceinline__ uint32_t clamp_ptr(int32_t p, uint32_t nnz) {
+    return p < 0 ? 0u : min((uint32_t)p, nnz);
+}
+
+// chunk_row[c] = first row r with rowptr[r] >= c * kChunkE (n_rows for c =
+// nchunk); also clears the big-row counter.
+__global__ __launch_bounds__(kThreads) void k_nbr_split(const int32_t *__restrict__ rowptr, uint32_t n_rows,
+                                                        uint32_t nnz, uint32_t nchunk,
+                                                        uint32_t *__restrict__ chunk_row,
+                                                        uint32_t *__restrict__ big_count) {
+    const uint32_t c = blockIdx.x * kThreads + threadIdx.x;
+    if (c == 0) *big_count = 0;
+    if (c > nchunk) return;
+    uint32_t lo = 0, hi = n_rows;
+    if (c == nchunk) {
+        lo = n_rows;
+    } else {
+        const uint32_t target = c * kChunkE;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (clamp_ptr(rowptr[mid], nnz) < target) lo = mid + 1;
+            else hi = mid;
+        }
+    }
+    chunk_row[c] = lo;
+}
+
+__global__ __launch_bounds__(kThreads) void k_nbr_chunk(const int32_t *__restrict__ rowptr,
+                                                        const int32_t *__restrict__ col, uint32_t n_cols,
+                                                        uint32_t nnz, uint32_t shift,
+                                                        const uint32_t *__restrict__ chunk_row,
+                                                        uint32_t *__restrict__ nd_out,
+                                                        uint32_t *__restrict__ big_list, uint32_t max_big,
+                                                        uint32_t *__restrict__ big_count, int32_t *flag) {
+    __shared__ uint32_t lines[kWin];
+    const uint32_t c = blockIdx.x;
+    const uint32_t r_lo = chunk_row[c], r_hi = chunk_row[c + 1];
+    if (r_lo >= r_hi) return;
+    // every row of the chunk that is not listed ends by (c+1)*kChunkE + kSmall
+    const uint32_t base = clamp_ptr(rowptr[r_lo], nnz);
+    const uint32_t wend = min(clamp_ptr(rowptr[r_hi], nnz), min(nnz, (c + 1) * kChunkE + kSmall));
+    const uint32_t cnt = wend > base ? min(wend - base, kWin) : 0u;
+    for (uint32_t i = threadIdx.x; i < cnt; i += kThreads) {
+        const uint32_t v = (uint32_t)col[base + i];
+        if (v >= n_cols) flag_range_error(flag);
+        lines[i] = v >> shift;
+    }
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wave = threadIdx.x / kWave;
+    constexpr uint32_t NW = kThreads / kWave;
+    for (uint32_t rb = r_lo + wave * kWave; rb < r_hi; rb += NW * kWave) {
+        const uint32_t r = rb + lane;
+        const bool valid = r < r_hi;
+        const uint32_t s = valid ? clamp_ptr(rowptr[r], nnz) : 0u;
+        const uint32_t e = valid ? clamp_ptr(rowptr[r + 1], nnz) : 0u;
+        const uint32_t d = e > s ? e - s : 0u;
+        const bool big = valid && d > kSmall;
+        if (big) {
+            const uint32_t i = atomicAdd(big_count, 1u);
+            if (i < max_big) big_list[i] = r;  // always, unless rowptr is malformed
+        }
+        // rows outside the staged window can only come from a malformed rowptr
+        const bool small = valid && d > 0 && !big && s >= base && s - base + d <= cnt;
+        uint32_t mine = 0;
+        for (uint64_t mk = __ballot(small); mk; mk &= mk - 1) {
+            const uint32_t j = (uint32_t)__builtin_ctzll(mk);
+            const uint32_t sj = __shfl(s - base, j, kWave), dj = __shfl(d, j, kWave);
+            const uint32_t nk = (dj + kWave - 1) / kWave;
+            uint32_t my[kSmall / kWave];
+            bool dup[kSmall / kWave];
+#pragma unroll
+            for (uint32_t k = 0; k < kSmall / kWave; ++k) {
+                const uint32_t q = lane + k * kWave;
+                my[k] = q < dj ? lines[sj + q] : 0u;
+                dup[k] = false;
+            }
+            // entry q repeats a line when an earlier entry t < q has it
+            for (uint32_t t = 0; t + 1 < dj; ++t) {
+                const uint32_t x = lines[sj + t];
+#pragma unroll
+                for (uint32_t k = 0; k < kSmall / kWave; ++k)
+                    if (k < nk) dup[k] |= (lane + k * kWave > t) && x == my[k];
+            }
+            uint32_t nd = 0;
+#pragma unroll
+            for (uint32_t k = 0; k < kSmall / kWave; ++k)
+                if (k < nk) nd += (uint32_t)__popcll(__ballot(lane + k * kWave < dj && !dup[k]));
+            if (lane == j) mine = nd;
+        }
+        if (valid && !big) nd_out[r] = mine;
+    }
+}
+
+__global__ __launch_bounds__(kBigThreads) void k_nbr_big(const int32_t *__restrict__ rowptr,
+                                                         const int32_t *__restrict__ col, uint32_t n_cols,
+                                                         uint32_t nnz, uint32_t shift,
+                                                         const uint32_t *__restrict__ big_list, uint32_t max_big,
+                                                         const uint32_t *__restrict__ big_count,
+                                                         uint32_t *__restrict__ nd_out, int32_t *flag) {
+    __shared__ uint32_t bm[kBitmapWords];
+    __shared__ uint32_t red[kBigThreads / kWave];
+    const uint32_t nbig = min(*big_count, max_big);
+    for (uint32_t i = blockIdx.x; i < nbig; i += gridDim.x) {
+        const uint32_t r = big_list[i];
+        const uint32_t s = clamp_ptr(rowptr[r], nnz), e = max(s, clamp_ptr(rowptr[r + 1], nnz));
+        // the row's line span (max of ~line gives the minimum)
+        uint32_t hi = 0, nlo = 0;
+        for (uint32_t k = s + threadIdx.x; k < e; k += kBigThreads) {
+            const uint32_t v = (uint32_t)col[k];
+            if (v >= n_cols) {
+                flag_range_error(flag);
+                continue;
+            }
+            hi = max(hi, v >> shift);
+            nlo = max(nlo, ~(v >> shift));
+        }
+        hi = block_reduce<kBigThreads>(hi, OpMax{}, red);
+        const uint32_t lo = ~block_reduce<kBigThreads>(nlo, OpMax{}, red);
+        uint32_t fresh = 0;
+        for (uint64_t p0 = lo; p0 <= hi; p0 += 32ull * kBitmapWords) {
+            const uint64_t span = min((uint64_t)hi - p0 + 1, 32ull * kBitmapWords);
+            const uint32_t words = (uint32_t)((span + 31) / 32);
+            for (uint32_t w = threadIdx.x; w < words; w += kBigThreads) bm[w] = 0;
+            __syncthreads();
+            for (uint32_t k = s + threadIdx.x; k < e; k += kBigThreads) {
+                const uint32_t v = (uint32_t)col[k];
+                if (v >= n_cols) continue;
+                const uint64_t l = v >> shift;
+                if (l < p0 || l >= p0 + span) continue;
+                const uint32_t b = (uint32_t)(l - p0);
+                const uint32_t bit = 1u << (b & 31);
+                fresh += (atomicOr(&bm[b >> 5], bit) & bit) == 0;
+            }
+            __syncthreads();
+        }
+        const uint32_t nd = block_reduce<kBigThreads>(fresh, OpSum{}, red);
+        if (threadIdx.x == 0) nd_out[r] = nd;
+    }
+}
+
+// Part p of the rows: the sum of nd/|N(v)| over its non-empty rows (each
+// thread in row order, then a fixed tree) and their number.
+__global__ __launch_bounds__(kThreads) void k_nbr_reduce(const int32_t *__restrict__ rowptr, uint32_t n_rows,
+                                                         uint32_t nnz, uint32_t per_part,
+                                                         const uint32_t *__restrict__ nd,
+                                                         double *__restrict__ part_sum,
+                                                         uint32_t *__restrict__ part_cnt) {
+    __shared__ double ls[kThreads];
+    __shared__ uint32_t lc[kThreads / kWave];
+    const uint32_t r0 = blockIdx.x * per_part;
+    const uint32_t r1 = min(n_rows, r0 + per_part);
+    double acc = 0.0;
+    uint32_t cnt = 0;
+    for (uint32_t r = r0 + threadIdx.x; r < r1; r += kThreads) {
+        const uint32_t s = clamp_ptr(rowptr[r], nnz), e = clamp_ptr(rowptr[r + 1], nnz);
+        if (e <= s) continue;
+        acc += (double)nd[r] / (double)(e - s);
+        ++cnt;
+    }
+    ls[threadIdx.x] = acc;
+    __syncthreads();
+    for (uint32_t h = kThreads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) ls[threadIdx.x] += ls[threadIdx.x + h];
+        __syncthreads();
+    }
+    cnt = block_reduce<kThreads>(cnt, OpSum{}, lc);
+    if (threadIdx.x == 0) {
+        part_sum[blockIdx.x] = ls[0];
+        part_cnt[blockIdx.x] = cnt;
+    }
+}
+
+__global__ __launch_bounds__(kParts) void k_nbr_final(const double *__restrict__ part_sum,
+                                                      const uint32_t *__restrict__ part_cnt, uint32_t parts,
+                                                      double *__restrict__ result) {
+    __shared__ double ls[kParts];
+    __shared__ uint32_t lc[kParts / kWave];
+    const uint32_t t = threadIdx.x;
+    ls[t] = t < parts ? part_sum[t] : 0.0;
+    const uint32_t c = t < parts ? part_cnt[t] : 0u;
+    __syncthreads();
+    for (uint32_t h = kParts / 2; h > 0; h >>= 1) {
+        if (t < h) ls[t] += ls[t + h];
+        __syncthreads();
+    }
+    const uint32_t total = block_reduce<kParts>(c, OpSum{}, lc);
+    if (t == 0) {
+        result[0] = ls[0];
+        result[1] = (double)total;
+    }
+}
+
+struct NbrLayout {
+    uint32_t nchunk = 0, parts = 0, per_part = 0, max_big = 0;
+    uint32_t *chunk_row = nullptr, *nd = nullptr, *big_list = nullptr, *big_count = nullptr, *part_cnt = nullptr;
+    double *part_sum = nullptr;
+    size_t bytes = 0;
+};
+
+NbrLayout nbr_layout(void *ws, int64_t n_rows, int64_t nnz) {
+    NbrLayout L;
+    L.nchunk = nnz > 0 ? ceil_div((uint64_t)nnz, kChunkE) : 1u;  // one chunk holds all rows when nnz = 0
+    L.per_part = n_rows > 0 ? ceil_div((uint64_t)n_rows, kParts) : 1;
+    L.parts = n_rows > 0 ? ceil_div((uint64_t)n_rows, L.per_part) : 0;
+    L.max_big = (uint32_t)((uint64_t)nnz / (kSmall + 1) + 1);
+    Carver c(ws);
+    L.chunk_row = c.take<uint32_t>(L.nchunk + 1ull);
+    L.nd = c.take<uint32_t>((size_t)n_rows);
+    L.big_list = c.take<uint32_t>(L.max_big);
+    L.big_count = c.take<uint32_t>(1);
+    L.part_sum = c.take<double>(kParts);
+    L.part_cnt = c.take<uint32_t>(kParts);
+    L.bytes = c.bytes();
+    return L;
+}
+
+}  // namespace
+}  // namespace boba
+
+using namespace boba;
+
+extern "C" size_t boba_nbr_workspace(int64_t n_rows, int64_t nnz) {
+    if (n_rows < 0 || nnz < 0) return 0;
+    return nbr_layout(nullptr, n_rows, nnz).bytes;
+}
+
+extern "C" boba_status boba_nbr(const int32_t *rowptr, const int32_t *col, int64_t n_rows, int64_t n_cols,
+                                int64_t nnz, int32_t line_ids, int32_t *lines_per_row, double *result, void *ws,
+                                size_t ws_bytes, hipStream_t stream) {
+    clear_error();
+    if (n_rows < 0 || n_cols < 0 || nnz < 0) return fail(BOBA_ERR_ARG, "boba_nbr: negative size");
+    if (n_rows >= (1ll << 31) || n_cols >= (1ll << 31) || nnz >= (1ll << 31))
+        return fail(BOBA_ERR_OVERFLOW, "boba_nbr: sizes must be < 2^31");
+    if (line_ids < 1 || line_ids > (1 << 30) || (line_ids & (line_ids - 1)))
+        return fail(BOBA_ERR_ARG, "boba_nbr: line_ids must be a power of two in [1, 2^30] (got %d)", line_ids);
+    if (!result) return fail(BOBA_ERR_ARG, "boba_nbr: result is NULL");
+    if (n_rows > 0 && !rowptr) return fail(BOBA_ERR_ARG, "boba_nbr: rowptr is NULL");
+    if (nnz > 0 && !col) return fail(BOBA_ERR_ARG, "boba_nbr: col is NULL");
+    const size_t need = boba_nbr_workspace(n_rows, nnz);
+    if (!ws || ws_bytes < need || ((uintptr_t)ws & 255u))
+        return fail(BOBA_ERR_WORKSPACE, "boba_nbr: workspace needs %zu bytes, 256-byte aligned (got %zu at %p)", need,
+                    ws_bytes, ws);
+    int32_t *flag = range_flag();
+    if (!flag) return BOBA_ERR_HIP;
+    const NbrLayout L = nbr_layout(ws, n_rows, nnz);
+    const uint32_t nr = (uint32_t)n_rows, nc = (uint32_t)n_cols, ne = (uint32_t)nnz;
+    const uint32_t shift = (uint32_t)__builtin_ctz((unsigned)line_ids);
+    uint32_t *nd = lines_per_row ? (uint32_t *)lines_per_row : L.nd;
+    if (nr > 0) {
+        BOBA_LAUNCH("nbr_split", k_nbr_split, dim3(ceil_div(L.nchunk + 1ull, kThreads)), dim3(kThreads), stream,
+                    rowptr, nr, ne, L.nchunk, L.chunk_row, L.big_count);
+        BOBA_LAUNCH("nbr_chunk", k_nbr_chunk, dim3(L.nchunk), dim3(kThreads), stream, rowptr, col, nc, ne, shift,
+                    (const uint32_t *)L.chunk_row, nd, L.big_list, L.max_big, L.big_count, flag);
+        const uint32_t grid_big = min(L.max_big, device_cus());
+        BOBA_LAUNCH("nbr_big", k_nbr_big, dim3(grid_big), dim3(kBigThreads), stream, rowptr, col, nc, ne, shift,
+                    (const uint32_t *)L.big_list, L.max_big, (const uint32_t *)L.big_count, nd, flag);
+        BOBA_LAUNCH("nbr_reduce", k_nbr_reduce, dim3(L.parts), dim3(kThreads), stream, rowptr, nr, ne, L.per_part,
+                    (const uint32_t *)nd, L.part_sum, L.part_cnt);
+    }
+    BOBA_LAUNCH("nbr_final", k_nbr_final, dim3(1), dim3(kParts), stream, (const double *)L.part_sum,
+                (const uint32_t *)L.part_cnt, L.parts, result);
+    return BOBA_OK;
+}

@@ -64,3 +64,24 @@ def full_path_check(g, boba, interleaved=False, check_spmv=True):
         err = rel_l2(host(y), y_ref)
         assert err <= SPMV_TOL, f"SpMV relative L2 {err:.3e} > {SPMV_TOL}"
     assert boba.boba_check_device_error() == boba.BOBA_OK
+
+
+def nbr_check(rowptr, col, n_cols, line_ids=32):
+    rowptr = np.ascontiguousarray(rowptr, np.int32)
+    col = np.ascontiguousarray(col, np.int32)
+    n_rows = rowptr.size - 1
+    from paper_2306_10410_amd import boba
+    over_n, over_ne, lines = boba.boba_nbr(dev(rowptr), dev(col), n_cols, line_ids, per_row=True)
+    r_n, r_ne, r_lines = oracle.nbr(rowptr, col, n_rows, line_ids, per_row=True)
+    assert np.array_equal(host(lines), r_lines), "distinct lines per row differ"
+    # both sums add the same non-negative per-row ratios (each the same IEEE
+    # quotient) in different orders: each is within (rows - 1) * 2^-53 of the
+    # exact sum, relative
+    tol = 2.0 * max(n_rows, 1) * 2.0 ** -53
+    assert abs(over_n - r_n) <= tol * abs(r_n), (over_n, r_n)
+    assert abs(over_ne - r_ne) <= tol * abs(r_ne), (over_ne, r_ne)
+    nonempty = int(np.count_nonzero(np.diff(rowptr)))
+    if nonempty:
+        assert round(over_n * n_rows / over_ne) == nonempty
+    assert boba.boba_check_device_error() == boba.BOBA_OK
+    return over_n, over_ne

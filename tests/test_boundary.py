@@ -132,6 +132,21 @@ def test_bin_by_dst_argument_errors(lib):
     assert lib.boba_bin_by_dst(None, None, 0, 0, 4, None, None, None, 0, None) == boba.BOBA_OK
 
 
+def test_nbr_argument_errors(lib):
+    need = lib.boba_nbr_workspace(5, 9)
+    assert need > 0 and lib.boba_nbr_workspace(-1, 9) == 0
+    A, B, R = FAKE, P(0x10100), P(0x10200)
+    for bad_line in (0, -32, 3, 48, (1 << 30) + 1):
+        assert lib.boba_nbr(A, B, 5, 5, 9, bad_line, None, R, A, need, None) == boba.BOBA_ERR_ARG, bad_line
+    assert lib.boba_nbr(A, B, 5, 5, 9, 32, None, None, A, need, None) == boba.BOBA_ERR_ARG       # result
+    assert lib.boba_nbr(None, B, 5, 5, 9, 32, None, R, A, need, None) == boba.BOBA_ERR_ARG      # rowptr
+    assert lib.boba_nbr(A, None, 5, 5, 9, 32, None, R, A, need, None) == boba.BOBA_ERR_ARG      # col
+    assert lib.boba_nbr(A, B, -5, 5, 9, 32, None, R, A, need, None) == boba.BOBA_ERR_ARG
+    assert lib.boba_nbr(A, B, 5, 5, 1 << 31, 32, None, R, A, need, None) == boba.BOBA_ERR_OVERFLOW
+    assert lib.boba_nbr(A, B, 5, 5, 9, 32, None, R, A, need - 1, None) == boba.BOBA_ERR_WORKSPACE
+    assert lib.boba_nbr(A, B, 5, 5, 9, 32, None, R, P(0x10104), need, None) == boba.BOBA_ERR_WORKSPACE
+
+
 def test_binding_refuses_host_tensors():
     import torch
     x = torch.zeros(4, dtype=torch.int32)

@@ -7,7 +7,7 @@ import torch
 
 import oracle
 from paper_2306_10410_amd import boba, graphgen
-from gpu_util import SPMV_TOL, bits_equal, dev, full_path_check, host, rel_l2, requires_gpu
+from gpu_util import SPMV_TOL, bits_equal, dev, full_path_check, host, nbr_check, rel_l2, requires_gpu
 
 pytestmark = [pytest.mark.gpu, requires_gpu]
 
@@ -60,6 +60,8 @@ def test_rmat24_csr_and_spmv(rmat24):
     err = rel_l2(host(y), oracle.spmv64(rp_ref, col_ref, val_ref, g.x))
     assert err <= SPMV_TOL, err
     assert boba.boba_check_device_error() == boba.BOBA_OK
+    del y, val
+    nbr_check(rp_ref, col_ref, g.n)  # every row's distinct lines (Sec. 5.2)
 
 
 @pytest.mark.timeout(600)

@@ -346,6 +346,55 @@ def test_nbr_closed_forms():
     over_n, over_nonempty = oracle.nbr(rowptr, col, 3)
     assert math.isclose(over_nonempty, (0.25 + 1.0) / 2)
     assert math.isclose(over_n, (0.25 + 1.0) / 3)
+    *_, per_row = oracle.nbr(rowptr, col, 3, per_row=True)
+    assert list(per_row) == [1, 3, 0]
+
+
+def test_nbr_line_width_extremes():
+    # one ID per line: distinct neighbours / degree (duplicates lower it);
+    # a line wider than every ID: one line per row, so the ratio is 1/degree
+    rowptr = np.array([0, 3, 3, 8, 9], np.int32)
+    col = np.array([5, 5, 5, 0, 1, 2, 1, 0, 7], np.int32)
+    over_n, over_nonempty, per_row = oracle.nbr(rowptr, col, 4, line_ids=1, per_row=True)
+    assert list(per_row) == [1, 0, 3, 1]
+    assert math.isclose(over_nonempty, (1 / 3 + 3 / 5 + 1) / 3) and math.isclose(over_n, (1 / 3 + 3 / 5 + 1) / 4)
+    _, over_nonempty, per_row = oracle.nbr(rowptr, col, 4, line_ids=1 << 20, per_row=True)
+    assert list(per_row) == [1, 0, 1, 1]
+    assert math.isclose(over_nonempty, (1 / 3 + 1 / 5 + 1) / 3)
+
+
+def test_nbr_ignores_order_inside_rows():
+    rng = np.random.default_rng(33)
+    n = 3000
+    deg = rng.integers(0, 40, n)
+    rowptr = np.concatenate([[0], np.cumsum(deg)]).astype(np.int32)
+    col = rng.integers(0, n, rowptr[-1]).astype(np.int32)
+    ref = oracle.nbr(rowptr, col, n, per_row=True)
+    shuffled = col.copy()
+    for v in range(n):
+        rng.shuffle(shuffled[rowptr[v]:rowptr[v + 1]])
+    got = oracle.nbr(rowptr, shuffled, n, per_row=True)
+    assert got[0] == ref[0] and np.array_equal(got[2], ref[2])
+
+
+def test_nbr_grid_counted_geometrically():
+    # W x H mesh in natural order with W a multiple of 32: ID r*W + c lies in
+    # line (r, c // 32), so up and down neighbours are lines of their own and
+    # left and right share a line unless c sits at a line edge (c % 32 in {0, 31})
+    W, H = 96, 7
+    s, d = graphgen.grid(H, W)
+    rowptr, col, _ = oracle.coo_to_csr(s, d, None, W * H)
+    total, lines = 0.0, []
+    for r in range(H):
+        for c in range(W):
+            nb = [(r + dr, c + dc) for dr, dc in ((-1, 0), (0, -1), (0, 1), (1, 0))
+                  if 0 <= r + dr < H and 0 <= c + dc < W]
+            k = len({(rr, cc // 32) for rr, cc in nb})
+            lines.append(k)
+            total += k / len(nb)
+    over_n, over_nonempty, per_row = oracle.nbr(rowptr, col, W * H, per_row=True)
+    assert list(per_row) == lines
+    assert math.isclose(over_n, total / (W * H), rel_tol=1e-12) and over_n == over_nonempty
 
 
 def test_bin_by_dst_pins():
