@@ -3,24 +3,29 @@
 // column IDs fall in (a line holds line_ids consecutive IDs) divided by
 // |N(v)|, duplicates counted in |N(v)| as they occur; the metric is the mean
 // of that ratio.
-//   split   the first row of every chunk of kChunkE entries (a row belongs to
-//           the chunk its first entry falls in)
+//   split   the first row of every chunk: chunks hold kChunkE items, an item
+//           being a row or an entry (row r starts at item r + rowptr[r]), so
+//           runs of empty rows are shared out like entries
 //   chunk   a workgroup per chunk stages the line IDs of its rows' entries in
-//           LDS; a wavefront per row counts the entries whose line no earlier
-//           entry of the row has (one broadcast LDS read per earlier entry).
-//           Rows longer than kSmall are put on a list.
+//           LDS; a lane per row of up to kTiny entries compares them in
+//           registers, a wavefront per longer row counts the entries whose
+//           line no earlier entry of the row has (one broadcast LDS read per
+//           earlier entry).  Rows longer than kSmall are put on a list.
 //   big     a workgroup per listed row: an LDS bitmap over up to 2^20 lines,
 //           one pass per 2^20 lines of the row's [min, max] line span; an
 //           entry is new when its bit was clear.
 //   reduce  the per-row ratios summed in a fixed order (per part of the rows,
 //           then over the parts), so the result is bit-reproducible.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace boba {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr uint32_t kChunkE = 2048;                // entries per chunk
+constexpr uint32_t kChunkE = 2048;                // items (rows + entries) per chunk
+constexpr uint32_t kTiny = 8;                     // longest row a single lane counts
 constexpr uint32_t kSmall = 256;                  // longest row a wavefront counts
 constexpr uint32_t kWin = kChunkE + kSmall;       // entries a chunk stages
 constexpr int kBigThreads = 1024;
@@ -31,8 +36,8 @@ __device__ __forceinline__ uint32_t clamp_ptr(int32_t p, uint32_t nnz) {
     return p < 0 ? 0u : min((uint32_t)p, nnz);
 }
 
-// chunk_row[c] = first row r with rowptr[r] >= c * kChunkE (n_rows for c =
-// nchunk); also clears the big-row counter.
+// chunk_row[c] = first row r with r + rowptr[r] >= c * kChunkE (n_rows for
+// c = nchunk); also clears the big-row counter.
 __global__ __launch_bounds__(kThreads) void k_nbr_split(const int32_t *__restrict__ rowptr, uint32_t n_rows,
                                                         uint32_t nnz, uint32_t nchunk,
                                                         uint32_t *__restrict__ chunk_row,
@@ -47,7 +52,7 @@ __global__ __launch_bounds__(kThreads) void k_nbr_split(const int32_t *__restric
         const uint32_t target = c * kChunkE;
         while (lo < hi) {
             const uint32_t mid = (lo + hi) >> 1;
-            if (clamp_ptr(rowptr[mid], nnz) < target) lo = mid + 1;
+            if (mid + clamp_ptr(rowptr[mid], nnz) < target) lo = mid + 1;
             else hi = mid;
         }
     }
@@ -65,9 +70,10 @@ __global__ __launch_bounds__(kThreads) void k_nbr_chunk(const int32_t *__restric
     const uint32_t c = blockIdx.x;
     const uint32_t r_lo = chunk_row[c], r_hi = chunk_row[c + 1];
     if (r_lo >= r_hi) return;
-    // every row of the chunk that is not listed ends by (c+1)*kChunkE + kSmall
+    // the chunk's rows start within kChunkE entries of the first one, so
+    // every row that is not listed ends by base + kChunkE + kSmall
     const uint32_t base = clamp_ptr(rowptr[r_lo], nnz);
-    const uint32_t wend = min(clamp_ptr(rowptr[r_hi], nnz), min(nnz, (c + 1) * kChunkE + kSmall));
+    const uint32_t wend = min(clamp_ptr(rowptr[r_hi], nnz), min(nnz, base + kChunkE + kSmall));
     const uint32_t cnt = wend > base ? min(wend - base, kWin) : 0u;
     for (uint32_t i = threadIdx.x; i < cnt; i += kThreads) {
         const uint32_t v = (uint32_t)col[base + i];
@@ -92,7 +98,19 @@ __global__ __launch_bounds__(kThreads) void k_nbr_chunk(const int32_t *__restric
         // rows outside the staged window can only come from a malformed rowptr
         const bool small = valid && d > 0 && !big && s >= base && s - base + d <= cnt;
         uint32_t mine = 0;
-        for (uint64_t mk = __ballot(small); mk; mk &= mk - 1) {
+        if (small && d <= kTiny) {
+            uint32_t x[kTiny];
+#pragma unroll
+            for (uint32_t q = 0; q < kTiny; ++q) x[q] = q < d ? lines[s - base + q] : 0u;
+#pragma unroll
+            for (uint32_t q = 0; q < kTiny; ++q) {
+                bool seen = q >= d;
+#pragma unroll
+                for (uint32_t t = 0; t < q; ++t) seen |= x[t] == x[q];
+                mine += !seen;
+            }
+        }
+        for (uint64_t mk = __ballot(small && d > kTiny); mk; mk &= mk - 1) {
             const uint32_t j = (uint32_t)__builtin_ctzll(mk);
             const uint32_t sj = __shfl(s - base, j, kWave), dj = __shfl(d, j, kWave);
             const uint32_t nk = (dj + kWave - 1) / kWave;
@@ -121,40 +139,51 @@ __global__ __launch_bounds__(kThreads) void k_nbr_chunk(const int32_t *__restric
     }
 }
 
+// A workgroup per listed row.  The bitmap (dynamic LDS, `words` words) covers
+// lines [p0, p0 + 32*words).  When all lines fit (`whole`), one pass over
+// [0, 32*words) serves every row; otherwise the row's [min, max] line span is
+// found first and covered in as many passes as it takes.
 __global__ __launch_bounds__(kBigThreads) void k_nbr_big(const int32_t *__restrict__ rowptr,
                                                          const int32_t *__restrict__ col, uint32_t n_cols,
-                                                         uint32_t nnz, uint32_t shift,
+                                                         uint32_t nnz, uint32_t shift, uint32_t words, bool whole,
                                                          const uint32_t *__restrict__ big_list, uint32_t max_big,
                                                          const uint32_t *__restrict__ big_count,
                                                          uint32_t *__restrict__ nd_out, int32_t *flag) {
-    __shared__ uint32_t bm[kBitmapWords];
+    extern __shared__ uint32_t bm[];
     __shared__ uint32_t red[kBigThreads / kWave];
     const uint32_t nbig = min(*big_count, max_big);
+    const uint64_t cover = 32ull * words;
     for (uint32_t i = blockIdx.x; i < nbig; i += gridDim.x) {
         const uint32_t r = big_list[i];
         const uint32_t s = clamp_ptr(rowptr[r], nnz), e = max(s, clamp_ptr(rowptr[r + 1], nnz));
-        // the row's line span (max of ~line gives the minimum)
-        uint32_t hi = 0, nlo = 0;
-        for (uint32_t k = s + threadIdx.x; k < e; k += kBigThreads) {
-            const uint32_t v = (uint32_t)col[k];
-            if (v >= n_cols) {
-                flag_range_error(flag);
-                continue;
+        uint64_t lo = 0, hi = cover - 1;
+        if (!whole) {
+            // the row's line span (max of ~line gives the minimum)
+            uint32_t h = 0, nl = 0;
+            for (uint32_t k = s + threadIdx.x; k < e; k += kBigThreads) {
+                const uint32_t v = (uint32_t)col[k];
+                if (v >= n_cols) {
+                    flag_range_error(flag);
+                    continue;
+                }
+                h = max(h, v >> shift);
+                nl = max(nl, ~(v >> shift));
             }
-            hi = max(hi, v >> shift);
-            nlo = max(nlo, ~(v >> shift));
+            hi = block_reduce<kBigThreads>(h, OpMax{}, red);
+            lo = ~block_reduce<kBigThreads>(nl, OpMax{}, red);
         }
-        hi = block_reduce<kBigThreads>(hi, OpMax{}, red);
-        const uint32_t lo = ~block_reduce<kBigThreads>(nlo, OpMax{}, red);
         uint32_t fresh = 0;
-        for (uint64_t p0 = lo; p0 <= hi; p0 += 32ull * kBitmapWords) {
-            const uint64_t span = min((uint64_t)hi - p0 + 1, 32ull * kBitmapWords);
-            const uint32_t words = (uint32_t)((span + 31) / 32);
-            for (uint32_t w = threadIdx.x; w < words; w += kBigThreads) bm[w] = 0;
+        for (uint64_t p0 = lo; p0 <= hi; p0 += cover) {
+            const uint64_t span = min(hi - p0 + 1, cover);
+            const uint32_t nw = (uint32_t)((span + 31) / 32);
+            for (uint32_t w = threadIdx.x; w < nw; w += kBigThreads) bm[w] = 0;
             __syncthreads();
             for (uint32_t k = s + threadIdx.x; k < e; k += kBigThreads) {
                 const uint32_t v = (uint32_t)col[k];
-                if (v >= n_cols) continue;
+                if (v >= n_cols) {
+                    if (whole) flag_range_error(flag);
+                    continue;
+                }
                 const uint64_t l = v >> shift;
                 if (l < p0 || l >= p0 + span) continue;
                 const uint32_t b = (uint32_t)(l - p0);
@@ -229,7 +258,8 @@ struct NbrLayout {
 
 NbrLayout nbr_layout(void *ws, int64_t n_rows, int64_t nnz) {
     NbrLayout L;
-    L.nchunk = nnz > 0 ? ceil_div((uint64_t)nnz, kChunkE) : 1u;  // one chunk holds all rows when nnz = 0
+    L.nchunk = ceil_div((uint64_t)n_rows + (uint64_t)nnz, kChunkE);
+    if (L.nchunk == 0) L.nchunk = 1;
     L.per_part = n_rows > 0 ? ceil_div((uint64_t)n_rows, kParts) : 1;
     L.parts = n_rows > 0 ? ceil_div((uint64_t)n_rows, L.per_part) : 0;
     L.max_big = (uint32_t)((uint64_t)nnz / (kSmall + 1) + 1);
@@ -281,9 +311,19 @@ extern "C" boba_status boba_nbr(const int32_t *rowptr, const int32_t *col, int64
                     rowptr, nr, ne, L.nchunk, L.chunk_row, L.big_count);
         BOBA_LAUNCH("nbr_chunk", k_nbr_chunk, dim3(L.nchunk), dim3(kThreads), stream, rowptr, col, nc, ne, shift,
                     (const uint32_t *)L.chunk_row, nd, L.big_list, L.max_big, L.big_count, flag);
-        const uint32_t grid_big = min(L.max_big, device_cus());
-        BOBA_LAUNCH("nbr_big", k_nbr_big, dim3(grid_big), dim3(kBigThreads), stream, rowptr, col, nc, ne, shift,
-                    (const uint32_t *)L.big_list, L.max_big, (const uint32_t *)L.big_count, nd, flag);
+        // a bitmap over all lines when they fit in 128 KB (2^20 lines), so
+        // that smaller ones let two or more workgroups share a CU
+        const uint64_t nlines = ((uint64_t)nc + (uint64_t)line_ids - 1) >> shift;
+        const bool whole = nlines <= 32ull * kBitmapWords;
+        const uint32_t words = whole ? (uint32_t)std::max<uint64_t>(1, (nlines + 31) / 32) : kBitmapWords;
+        const uint32_t per_cu = std::max<uint32_t>(1, std::min<uint32_t>(2, (uint32_t)(147456 / (4ull * words))));
+        const uint32_t grid_big = std::min<uint64_t>(L.max_big, (uint64_t)device_cus() * per_cu);
+        const int tok = timing_begin("nbr_big", stream);
+        hipLaunchKernelGGL(k_nbr_big, dim3(grid_big), dim3(kBigThreads), 4ull * words, stream, rowptr, col, nc, ne,
+                           shift, words, whole, (const uint32_t *)L.big_list, L.max_big,
+                           (const uint32_t *)L.big_count, nd, flag);
+        timing_end(tok, stream);
+        if (boba_status e = check_launch("nbr_big")) return e;
         BOBA_LAUNCH("nbr_reduce", k_nbr_reduce, dim3(L.parts), dim3(kThreads), stream, rowptr, nr, ne, L.per_part,
                     (const uint32_t *)nd, L.part_sum, L.part_cnt);
     }

@@ -49,6 +49,19 @@ def test_rows_around_the_wavefront_limit_and_chunk_edges():
     nbr_check(rowptr, col, n, line_ids=1)
 
 
+def test_long_runs_of_empty_rows():
+    # chunks count rows as well as entries: 100,000 empty rows in the middle
+    # and 200,000 at the end (where BOBA puts isolated vertices) are shared
+    # out over many chunks
+    rng = np.random.default_rng(100)
+    deg = np.concatenate([rng.integers(0, 40, 3000), np.zeros(100000, np.int64), rng.integers(0, 400, 2000),
+                          np.zeros(200000, np.int64)])
+    rowptr = np.concatenate([[0], np.cumsum(deg)]).astype(np.int32)
+    n = deg.size
+    col = rng.integers(0, n, rowptr[-1]).astype(np.int32)
+    nbr_check(rowptr, col, n)
+
+
 def test_hub_rows_with_several_bitmap_passes():
     # one ID per line and 2^22 columns: a hub row spanning all of them takes
     # four passes of the 2^20-line bitmap; a second hub covers a narrow span
