@@ -316,6 +316,9 @@ def main():
     del ws_nbr
     assert boba.boba_check_device_error() == boba.BOBA_OK
 
+    pagerank = bench_pagerank(src, dst, s2, d2, perm, n, m, dev, ws_c)
+    log(f"PageRank x{pagerank['iters']}: {pagerank['ms_before']:.2f} -> {pagerank['ms_after']:.2f} ms")
+
     binned = None
     if args.bin_bits > 0:
         binned = bench_binned(args, g, src, dst, val, x, dev, ws_rr, ws_c, ws_s, before_spmv_ms)
@@ -382,12 +385,47 @@ def main():
         "batched": batched,
         "binned": binned,
         "nbr": nbr,
+        "pagerank": pagerank,
         "paper_context": PAPER_CONTEXT,
         "device": torch.cuda.get_device_name(0),
         "source_digest": source_digest(),
     }
     print(json.dumps(out), flush=True)
     return 0
+
+
+def bench_pagerank(src, dst, s2, d2, perm, n, m, dev, ws_c, iters=20, reps=3):
+    """PageRank (the PR application of Sec. 5.1): `iters` pull-SpMV iterations
+    over the transposed CSR, on the input labels and on the BOBA labels."""
+    import numpy as np
+    import torch
+
+    from paper_2306_10410_amd import boba
+    rpT = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    colT = torch.empty(m, dtype=torch.int32, device=dev)
+    ws = torch.empty(boba.boba_pagerank_workspace(n, m), dtype=torch.uint8, device=dev)
+    out, ranks = {"iters": iters, "damping": 0.85}, {}
+    for name, (a, b) in (("before", (src, dst)), ("after", (s2, d2))):
+        boba.coo_to_csr(b, a, None, n, ws=ws_c, out=(rpT, colT, None))  # row v: sources of edges into v
+        rank = torch.empty(n, dtype=torch.float32, device=dev)
+        boba.boba_pagerank(rpT, colT, 0.85, iters, rank=rank, ws=ws)
+        times = []
+        for _ in range(reps):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            e[0].record()
+            boba.boba_pagerank(rpT, colT, 0.85, iters, rank=rank, ws=ws)
+            e[1].record()
+            torch.cuda.synchronize()
+            times.append(e[0].elapsed_time(e[1]))
+        out[f"ms_{name}"] = float(np.median(times))
+        ranks[name] = rank
+    out["speedup"] = out["ms_before"] / out["ms_after"]
+    out["ms_per_iter_after"] = out["ms_after"] / iters
+    # the same ranks, relabelled: rank_after[perm[v]] = rank_before[v]
+    out["rank_reordered_vs_input_l1"] = float((ranks["after"][perm.long()].double()
+                                               - ranks["before"].double()).abs().sum())
+    assert boba.boba_check_device_error() == boba.BOBA_OK
+    return out
 
 
 def bench_binned(args, g, src, dst, val, x, dev, ws_rr, ws_c, ws_s, before_spmv_ms, reps=5):

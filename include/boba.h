@@ -192,6 +192,35 @@ BOBA_API boba_status boba_bin_by_dst(const int32_t *src, const int32_t *dst, int
                                      int32_t *src_out, int32_t *dst_out, void *ws, size_t ws_bytes,
                                      hipStream_t stream);
 
+/* ------------------------------------------------------------ PageRank ---
+ * PageRank, the iterative application of Sec. 5.1, as repeated SpMV
+ * (Algorithm 3, pull form) over the transposed graph:
+ *   r_0 = 1/n,  r_{k+1}[v] = (1 - damping)/n + damping * (sum_{u->v} r_k[u] / outdeg(u) + D_k / n)
+ * where outdeg(u) counts the edges leaving u and D_k is the rank held by
+ * vertices with no out-edge (spread evenly).  FP32 ranks and SpMV; the
+ * reductions (D_k, the residual) in FP64 in a fixed order: bit-reproducible.
+ *   rowptr, col  CSR of the transposed graph: row v lists the sources u of
+ *                the edges u -> v (coo_to_csr(dst, src, ...)); int32[n+1],
+ *                int32[nnz] (col NULL when nnz = 0).  Column IDs outside
+ *                [0, n) are skipped and flagged (boba_check_device_error).
+ *   damping      in [0, 1] (0.85 is the usual choice).
+ *   max_iter     iterations to run (>= 0).
+ *   tol          > 0: stop after the first iteration k whose L1 change
+ *                sum_v |r_{k+1}[v] - r_k[v]| is below tol; 0: run all max_iter.
+ *   rank         float[n] output (device).
+ *   residual     device double[max_iter] or NULL: the L1 change of every
+ *                iteration run (entries past the last one are not written).
+ *   iters        device int32[1] or NULL: iterations run.
+ *   ws           at least boba_pagerank_workspace(n, nnz) bytes, 256-byte aligned.
+ * n = 0 writes nothing.  The call does not wait for the device: the stop
+ * test runs on the device, and the iterations after it return at once.
+ * Errors: ERR_ARG (NULL, damping, max_iter, tol), ERR_OVERFLOW (a size >= 2^31),
+ * ERR_WORKSPACE, ERR_HIP. */
+BOBA_API size_t boba_pagerank_workspace(int64_t n, int64_t nnz);
+BOBA_API boba_status boba_pagerank(const int32_t *rowptr, const int32_t *col, int64_t n, int64_t nnz,
+                                   float damping, int32_t max_iter, double tol, float *rank, double *residual,
+                                   int32_t *iters, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* ----------------------------------------------------------------- NBR ---
  * The spatial-locality metric of Sec. 5.2 over the rows of a CSR matrix: for
  * every row v with a non-empty neighbourhood N(v) (its column IDs, duplicates

@@ -7,7 +7,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 The arithmetic lives in ``boba_oracle.c`` (plain sequential C, FP64 where
 floating point is involved); this module only compiles it with gcc, loads it
 with ctypes and marshals numpy arrays.  ``features.py`` holds the plain numpy
-definition of the selector's graph features.
+definition of the selector's graph features, and ``pagerank`` below is plain
+numpy in FP64.
 """
 from __future__ import annotations
 
@@ -169,3 +170,30 @@ def nbr(rowptr, col, n, line_ids=32, per_row=False):
     _check(lib().oracle_nbr(_p(rowptr), _p(col), n, line_ids, _p(s), _p(c), _p(d) if per_row else None), "nbr")
     means = (s[0] / n if n else 0.0), (s[0] / c[0] if c[0] else 0.0)
     return (*means, d) if per_row else means
+
+
+def pagerank(src, dst, n, damping=0.85, iters=20, tol=0.0):
+    """PageRank by power iteration (the PR application of Sec. 5.1), in FP64,
+    straight from its definition over the edge list:
+        r_0 = 1/n
+        r_{k+1}[v] = (1 - d)/n + d * (sum over edges u->v of r_k[u]/outdeg(u) + D_k/n)
+    with D_k the rank on vertices without out-edges.  Stops after the first
+    iteration whose L1 change is below tol (tol > 0).  Returns (r, the L1
+    change of every iteration run)."""
+    src = np.asarray(src, np.int64)
+    dst = np.asarray(dst, np.int64)
+    outdeg = np.bincount(src, minlength=n).astype(np.float64)
+    r = np.full(n, 1.0 / n)
+    changes = []
+    for _ in range(iters):
+        share = np.zeros(n)
+        np.divide(r, outdeg, out=share, where=outdeg > 0)
+        y = np.zeros(n)
+        np.add.at(y, dst, share[src])  # every edge u->v carries r[u]/outdeg(u) to v
+        dangling = r[outdeg == 0].sum()
+        new = (1.0 - damping) / n + damping * (y + dangling / n)
+        changes.append(float(np.abs(new - r).sum()))
+        r = new
+        if tol > 0 and changes[-1] < tol:
+            break
+    return r, changes

@@ -36,6 +36,8 @@ PROTOTYPES = {
     "coo_to_csr": (_I32, [_P, _P, _P, _I64, _I64, _P, _P, _P, _P, _SZ, _P]),
     "spmv_csr_workspace": (_SZ, [_I64, _I64]),
     "spmv_csr": (_I32, [_P, _P, _P, _I64, _I64, _I64, _P, _P, _P, _SZ, _P]),
+    "boba_pagerank_workspace": (_SZ, [_I64, _I64]),
+    "boba_pagerank": (_I32, [_P, _P, _I64, _I64, ctypes.c_float, _I32, ctypes.c_double, _P, _P, _P, _P, _SZ, _P]),
     "boba_nbr_workspace": (_SZ, [_I64, _I64]),
     "boba_nbr": (_I32, [_P, _P, _I64, _I64, _I64, _I32, _P, _P, _P, _SZ, _P]),
     "boba_batch_workspace": (_SZ, [_I32, _P, _P, _P]),
@@ -217,6 +219,29 @@ def spmv_csr(rowptr, col, val, x, *, y=None, ws=None, stream=None):
     _check(load().spmv_csr(_ptr(rowptr), _ptr(col), _ptr(val), n_rows, x.numel(), col.numel(), _ptr(x), _ptr(y),
                            _ptr(ws), ws.numel(), _stream(stream)))
     return y
+
+
+def boba_pagerank_workspace(n: int, nnz: int) -> int:
+    return int(load().boba_pagerank_workspace(n, nnz))
+
+
+def boba_pagerank(rowptr, col, damping: float = 0.85, max_iter: int = 20, tol: float = 0.0, *, rank=None,
+                  ws=None, stream=None):
+    """PageRank over the transposed CSR (row v lists the sources of the edges
+    into v).  Returns (rank float32[n], residual float64[max_iter], iters
+    int32[1]), all device tensors; residual entries past iters are unset."""
+    _dev_i32(rowptr, "rowptr")
+    _dev_i32(col, "col")
+    n = rowptr.numel() - 1
+    dev = rowptr.device
+    rank = torch.empty(max(n, 0), dtype=torch.float32, device=dev) if rank is None else rank
+    residual = torch.full((max(max_iter, 0),), float("nan"), dtype=torch.float64, device=dev)
+    iters = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws = _workspace(boba_pagerank_workspace(n, col.numel()), dev, ws)
+    _check(load().boba_pagerank(_ptr(rowptr), _ptr(col), n, col.numel(), damping, max_iter, tol, _ptr(rank),
+                                _ptr(residual) if max_iter > 0 else None, _ptr(iters), _ptr(ws), ws.numel(),
+                                _stream(stream)))
+    return rank, residual, iters
 
 
 def boba_nbr_workspace(n_rows: int, nnz: int) -> int:

@@ -14,6 +14,20 @@
 //   fixup   every row crossing chunk boundaries is summed from its tail
 //           partial and the following head partials, in chunk order.
 // Every sum has a fixed order, so results are bit-reproducible.
+//
+// PageRank as repeated SpMV (the PR application of Sec. 5.1; the paper's PR
+// pushes ranks along edges with atomics, here the same iteration is pulled
+// with Algorithm 3 over the transposed CSR, which needs no atomics):
+//   r_{k+1}[v] = (1 - a)/n + a * (sum_{u -> v} r_k[u] / outdeg(u) + D_k / n)
+// with damping a, r_0 = 1/n, and D_k the rank on vertices without out-edges.
+//   init / outdeg   r = 1/n, out-degrees counted from the columns
+//   step            per part of the vertices: x = r / outdeg (the SpMV's
+//                   input), the partial dangling mass and, after an SpMV,
+//                   the new rank and the partial L1 change (fused)
+//   finish          one workgroup sums the partials in a fixed order, keeps
+//                   D and the residual, and raises the stop flag once the
+//                   residual is below the tolerance; every later kernel of
+//                   the call then returns at once.
 #include "internal.h"
 
 namespace boba {
@@ -71,7 +85,9 @@ __global__ __launch_bounds__(kThreads) void k_spmv_chunk(const int32_t *__restri
                                                          const uint32_t *__restrict__ split_j,
                                                          float *__restrict__ y, uint32_t *__restrict__ head_row,
                                                          float *__restrict__ head_sum, uint32_t *__restrict__ tail_row,
-                                                         float *__restrict__ tail_sum, int32_t *flag) {
+                                                         float *__restrict__ tail_sum, int32_t *flag,
+                                                         const uint32_t *__restrict__ skip) {
+    if (skip && *skip) return;  // a converged PageRank iteration
     __shared__ float prod[kChunk];
     __shared__ uint32_t long_rows[kChunk / kShort + 1];
     __shared__ uint32_t n_long;
@@ -150,7 +166,9 @@ __global__ __launch_bounds__(kThreads) void k_spmv_chunk(const int32_t *__restri
 __global__ __launch_bounds__(kThreads) void k_spmv_fixup(uint32_t nchunk, const uint32_t *__restrict__ head_row,
                                                          const float *__restrict__ head_sum,
                                                          const uint32_t *__restrict__ tail_row,
-                                                         const float *__restrict__ tail_sum, float *__restrict__ y) {
+                                                         const float *__restrict__ tail_sum, float *__restrict__ y,
+                                                         const uint32_t *__restrict__ skip) {
+    if (skip && *skip) return;
     const uint32_t stride = gridDim.x * kThreads;
     for (uint32_t c = blockIdx.x * kThreads + threadIdx.x; c < nchunk; c += stride) {
         const uint32_t r = tail_row[c];
@@ -164,6 +182,111 @@ __global__ __launch_bounds__(kThreads) void k_spmv_fixup(uint32_t nchunk, const 
 __global__ __launch_bounds__(kThreads) void k_fill_f32(float *__restrict__ a, uint32_t count, float v) {
     const uint32_t stride = gridDim.x * kThreads;
     for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < count; i += stride) a[i] = v;
+}
+
+constexpr uint32_t kPrParts = 4096;  // parts of the vertices in the reductions
+
+__global__ __launch_bounds__(kThreads) void k_pr_init(uint32_t n, float *__restrict__ rank,
+                                                      uint32_t *__restrict__ outdeg, uint32_t *__restrict__ state) {
+    const uint32_t stride = gridDim.x * kThreads;
+    const float r0 = 1.f / (float)n;
+    for (uint32_t v = blockIdx.x * kThreads + threadIdx.x; v < n; v += stride) {
+        rank[v] = r0;
+        outdeg[v] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        state[0] = 0;  // stop flag
+        state[1] = 0;  // iterations done
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_pr_outdeg(const int32_t *__restrict__ col, uint32_t nnz, uint32_t n,
+                                                        uint32_t *__restrict__ outdeg, int32_t *flag) {
+    const uint32_t stride = gridDim.x * kThreads;
+    bool bad = false;
+    for (uint32_t e = blockIdx.x * kThreads + threadIdx.x; e < nnz; e += stride) {
+        const uint32_t u = (uint32_t)col[e];
+        if (u < n) atomicAdd(&outdeg[u], 1u);
+        else bad = true;
+    }
+    if (bad) flag_range_error(flag);
+}
+
+// Fixed-order sum over the workgroup of two doubles per thread; thread 0 gets
+// the totals.
+template <int BLOCK>
+__device__ inline void block_sum2(double &a, double &b, double *la, double *lb) {
+    la[threadIdx.x] = a;
+    lb[threadIdx.x] = b;
+    __syncthreads();
+    for (int h = BLOCK / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            la[threadIdx.x] += la[threadIdx.x + h];
+            lb[threadIdx.x] += lb[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    a = la[0];
+    b = lb[0];
+}
+
+// Part p of the vertices.  UPDATE: the new rank from y (the SpMV of x) and
+// the dangling mass D kept by the last finish.  Then x = r / outdeg for the
+// next SpMV and the part's dangling mass (and L1 change).
+template <bool UPDATE>
+__global__ __launch_bounds__(kThreads) void k_pr_step(uint32_t n, uint32_t per_part, float base, float damping,
+                                                      const double *__restrict__ dangling,
+                                                      const float *__restrict__ y, float *__restrict__ rank,
+                                                      const uint32_t *__restrict__ outdeg, float *__restrict__ x,
+                                                      double *__restrict__ part_dang, double *__restrict__ part_diff,
+                                                      const uint32_t *__restrict__ skip) {
+    if (UPDATE && *skip) return;
+    __shared__ double la[kThreads], lb[kThreads];
+    const float dn = UPDATE ? (float)(*dangling / (double)n) : 0.f;
+    const uint32_t v0 = blockIdx.x * per_part, v1 = min(n, v0 + per_part);
+    double dang = 0.0, diff = 0.0;
+    for (uint32_t v = v0 + threadIdx.x; v < v1; v += kThreads) {
+        float r = rank[v];
+        if (UPDATE) {
+            const float nr = base + damping * (y[v] + dn);
+            diff += fabs((double)nr - (double)r);
+            rank[v] = nr;
+            r = nr;
+        }
+        const uint32_t d = outdeg[v];
+        x[v] = d ? r / (float)d : 0.f;
+        if (!d) dang += r;
+    }
+    block_sum2<kThreads>(dang, diff, la, lb);
+    if (threadIdx.x == 0) {
+        part_dang[blockIdx.x] = dang;
+        part_diff[blockIdx.x] = diff;
+    }
+}
+
+// Sums the partials (thread t takes parts t, t + 1024, ... in order, then a
+// fixed tree).  it < 0: after init (no residual).
+__global__ __launch_bounds__(1024) void k_pr_finish(uint32_t parts, const double *__restrict__ part_dang,
+                                                    const double *__restrict__ part_diff, int32_t it, double tol,
+                                                    double *__restrict__ dangling, double *__restrict__ residual,
+                                                    uint32_t *__restrict__ state, int32_t *__restrict__ iters_out) {
+    if (it >= 0 && state[0]) return;
+    __shared__ double la[1024], lb[1024];
+    double dang = 0.0, diff = 0.0;
+    for (uint32_t p = threadIdx.x; p < parts; p += 1024) {
+        dang += part_dang[p];
+        diff += part_diff[p];
+    }
+    block_sum2<1024>(dang, diff, la, lb);
+    if (threadIdx.x == 0) {
+        *dangling = dang;
+        if (it >= 0) {
+            if (residual) residual[it] = diff;
+            state[1] = (uint32_t)it + 1;
+            if (tol > 0.0 && diff < tol) state[0] = 1;
+        }
+        if (iters_out) *iters_out = (int32_t)state[1];
+    }
 }
 
 struct SpmvLayout {
@@ -224,13 +347,104 @@ extern "C" boba_status spmv_csr(const int32_t *rowptr, const int32_t *col, const
     if (val)
         BOBA_LAUNCH("spmv", (k_spmv_chunk<true>), dim3(L.nchunk), dim3(kThreads), stream, rowptr, col, val, nr, nc,
                     (int32_t)nnz, x, (const uint32_t *)L.split_i, (const uint32_t *)L.split_j, y, L.head_row,
-                    L.head_sum, L.tail_row, L.tail_sum, flag);
+                    L.head_sum, L.tail_row, L.tail_sum, flag, (const uint32_t *)nullptr);
     else
         BOBA_LAUNCH("spmv", (k_spmv_chunk<false>), dim3(L.nchunk), dim3(kThreads), stream, rowptr, col, val, nr, nc,
                     (int32_t)nnz, x, (const uint32_t *)L.split_i, (const uint32_t *)L.split_j, y, L.head_row,
-                    L.head_sum, L.tail_row, L.tail_sum, flag);
+                    L.head_sum, L.tail_row, L.tail_sum, flag, (const uint32_t *)nullptr);
     BOBA_LAUNCH("spmv_fixup", k_spmv_fixup, dim3(grid_for(L.nchunk, kThreads)), dim3(kThreads), stream, L.nchunk,
                 (const uint32_t *)L.head_row, (const float *)L.head_sum, (const uint32_t *)L.tail_row,
-                (const float *)L.tail_sum, y);
+                (const float *)L.tail_sum, y, (const uint32_t *)nullptr);
+    return BOBA_OK;
+}
+
+// ------------------------------------------------------------- PageRank ---
+struct PrLayout {
+    uint32_t parts = 0, per_part = 0;
+    uint32_t *outdeg = nullptr, *state = nullptr;
+    float *x = nullptr, *y = nullptr;
+    double *part_dang = nullptr, *part_diff = nullptr, *dangling = nullptr;
+    void *spmv_ws = nullptr;
+    size_t spmv_bytes = 0, bytes = 0;
+};
+
+static PrLayout pr_layout(void *ws, int64_t n, int64_t nnz) {
+    PrLayout L;
+    L.per_part = n > 0 ? ceil_div((uint64_t)n, kPrParts) : 1;
+    L.parts = n > 0 ? ceil_div((uint64_t)n, L.per_part) : 0;
+    Carver c(ws);
+    L.outdeg = c.take<uint32_t>((size_t)n);
+    L.x = c.take<float>((size_t)n);
+    L.y = c.take<float>((size_t)n);
+    L.part_dang = c.take<double>(kPrParts);
+    L.part_diff = c.take<double>(kPrParts);
+    L.dangling = c.take<double>(1);
+    L.state = c.take<uint32_t>(2);
+    L.spmv_bytes = spmv_layout(nullptr, n, nnz).bytes;
+    L.spmv_ws = c.take<char>(L.spmv_bytes);
+    L.bytes = c.bytes();
+    return L;
+}
+
+extern "C" size_t boba_pagerank_workspace(int64_t n, int64_t nnz) {
+    if (n < 0 || nnz < 0) return 0;
+    return pr_layout(nullptr, n, nnz).bytes;
+}
+
+extern "C" boba_status boba_pagerank(const int32_t *rowptr, const int32_t *col, int64_t n, int64_t nnz,
+                                     float damping, int32_t max_iter, double tol, float *rank, double *residual,
+                                     int32_t *iters, void *ws, size_t ws_bytes, hipStream_t stream) {
+    clear_error();
+    if (n < 0 || nnz < 0) return fail(BOBA_ERR_ARG, "boba_pagerank: negative size");
+    if (n >= (1ll << 31) || nnz >= (1ll << 31)) return fail(BOBA_ERR_OVERFLOW, "boba_pagerank: sizes must be < 2^31");
+    if (!(damping >= 0.f && damping <= 1.f))
+        return fail(BOBA_ERR_ARG, "boba_pagerank: damping must lie in [0, 1] (got %g)", (double)damping);
+    if (max_iter < 0) return fail(BOBA_ERR_ARG, "boba_pagerank: max_iter < 0");
+    if (!(tol >= 0.0)) return fail(BOBA_ERR_ARG, "boba_pagerank: tol must be >= 0");
+    if (n == 0) return BOBA_OK;
+    if (!rowptr || !rank) return fail(BOBA_ERR_ARG, "boba_pagerank: rowptr or rank is NULL");
+    if (nnz > 0 && !col) return fail(BOBA_ERR_ARG, "boba_pagerank: col is NULL");
+    const size_t need = boba_pagerank_workspace(n, nnz);
+    if (!ws || ws_bytes < need || ((uintptr_t)ws & 255u))
+        return fail(BOBA_ERR_WORKSPACE, "boba_pagerank: workspace needs %zu bytes, 256-byte aligned (got %zu at %p)",
+                    need, ws_bytes, ws);
+    int32_t *flag = range_flag();
+    if (!flag) return BOBA_ERR_HIP;
+    const PrLayout L = pr_layout(ws, n, nnz);
+    const SpmvLayout S = spmv_layout(L.spmv_ws, n, nnz);
+    const uint32_t un = (uint32_t)n, ue = (uint32_t)nnz;
+    const float base = (1.f - damping) / (float)un;
+    BOBA_LAUNCH("pr_init", k_pr_init, dim3(grid_for(un, kThreads * 4)), dim3(kThreads), stream, un, rank, L.outdeg,
+                L.state);
+    if (ue > 0) {
+        BOBA_LAUNCH("pr_outdeg", k_pr_outdeg, dim3(grid_for(ue, kThreads * 4)), dim3(kThreads), stream, col, ue, un,
+                    L.outdeg, flag);
+        BOBA_LAUNCH("spmv_split", k_spmv_split, dim3(ceil_div(S.nchunk + 1ull, kThreads)), dim3(kThreads), stream,
+                    rowptr, un, (int32_t)ue, S.nchunk, S.split_i, S.split_j);
+    }
+    BOBA_LAUNCH("pr_step", k_pr_step<false>, dim3(L.parts), dim3(kThreads), stream, un, L.per_part, base, damping,
+                (const double *)L.dangling, (const float *)L.y, rank, (const uint32_t *)L.outdeg, L.x, L.part_dang,
+                L.part_diff, (const uint32_t *)L.state);
+    BOBA_LAUNCH("pr_finish", k_pr_finish, dim3(1), dim3(1024), stream, L.parts, (const double *)L.part_dang,
+                (const double *)L.part_diff, -1, tol, L.dangling, residual, L.state, iters);
+    for (int32_t it = 0; it < max_iter; ++it) {
+        if (ue > 0) {
+            BOBA_LAUNCH("spmv", (k_spmv_chunk<false>), dim3(S.nchunk), dim3(kThreads), stream, rowptr, col,
+                        (const float *)nullptr, un, un, (int32_t)ue, (const float *)L.x,
+                        (const uint32_t *)S.split_i, (const uint32_t *)S.split_j, L.y, S.head_row, S.head_sum,
+                        S.tail_row, S.tail_sum, flag, (const uint32_t *)L.state);
+            BOBA_LAUNCH("spmv_fixup", k_spmv_fixup, dim3(grid_for(S.nchunk, kThreads)), dim3(kThreads), stream,
+                        S.nchunk, (const uint32_t *)S.head_row, (const float *)S.head_sum,
+                        (const uint32_t *)S.tail_row, (const float *)S.tail_sum, L.y, (const uint32_t *)L.state);
+        } else {
+            BOBA_LAUNCH("spmv_fill", k_fill_f32, dim3(grid_for(un, kThreads * 4)), dim3(kThreads), stream, L.y, un,
+                        0.f);
+        }
+        BOBA_LAUNCH("pr_step", k_pr_step<true>, dim3(L.parts), dim3(kThreads), stream, un, L.per_part, base, damping,
+                    (const double *)L.dangling, (const float *)L.y, rank, (const uint32_t *)L.outdeg, L.x,
+                    L.part_dang, L.part_diff, (const uint32_t *)L.state);
+        BOBA_LAUNCH("pr_finish", k_pr_finish, dim3(1), dim3(1024), stream, L.parts, (const double *)L.part_dang,
+                    (const double *)L.part_diff, it, tol, L.dangling, residual, L.state, iters);
+    }
     return BOBA_OK;
 }

@@ -147,6 +147,23 @@ def test_nbr_argument_errors(lib):
     assert lib.boba_nbr(A, B, 5, 5, 9, 32, None, R, P(0x10104), need, None) == boba.BOBA_ERR_WORKSPACE
 
 
+def test_pagerank_argument_errors(lib):
+    need = lib.boba_pagerank_workspace(5, 9)
+    assert need > 0 and lib.boba_pagerank_workspace(5, -1) == 0
+    A, B, R = FAKE, P(0x10100), P(0x10200)
+    for damping in (-0.1, 1.5, float("nan")):
+        assert lib.boba_pagerank(A, B, 5, 9, damping, 3, 0.0, R, None, None, A, need, None) == boba.BOBA_ERR_ARG
+    assert lib.boba_pagerank(A, B, 5, 9, 0.85, -1, 0.0, R, None, None, A, need, None) == boba.BOBA_ERR_ARG
+    assert lib.boba_pagerank(A, B, 5, 9, 0.85, 3, -1e-3, R, None, None, A, need, None) == boba.BOBA_ERR_ARG
+    assert lib.boba_pagerank(A, B, 5, 9, 0.85, 3, float("nan"), R, None, None, A, need, None) == boba.BOBA_ERR_ARG
+    assert lib.boba_pagerank(None, B, 5, 9, 0.85, 3, 0.0, R, None, None, A, need, None) == boba.BOBA_ERR_ARG
+    assert lib.boba_pagerank(A, None, 5, 9, 0.85, 3, 0.0, R, None, None, A, need, None) == boba.BOBA_ERR_ARG
+    assert lib.boba_pagerank(A, B, 5, 9, 0.85, 3, 0.0, None, None, None, A, need, None) == boba.BOBA_ERR_ARG
+    assert lib.boba_pagerank(A, B, 1 << 31, 9, 0.85, 3, 0.0, R, None, None, A, need, None) == boba.BOBA_ERR_OVERFLOW
+    assert lib.boba_pagerank(A, B, 5, 9, 0.85, 3, 0.0, R, None, None, A, need - 1, None) == boba.BOBA_ERR_WORKSPACE
+    assert lib.boba_pagerank(None, None, 0, 0, 0.85, 3, 0.0, None, None, None, None, 0, None) == boba.BOBA_OK
+
+
 def test_binding_refuses_host_tensors():
     import torch
     x = torch.zeros(4, dtype=torch.int32)

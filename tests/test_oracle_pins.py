@@ -419,3 +419,59 @@ def test_bin_by_dst_pins():
     assert list(do) == [0, 1, 0, 3, 2] and list(so) == [11, 13, 14, 10, 12]
     with pytest.raises(Exception):
         oracle.bin_by_dst(src, np.array([0, 1, 2, 3, 4], np.int32), 4, 2)  # out of range
+
+
+# -------------------------------------------------------------- PageRank
+def test_pagerank_directed_cycle_stays_uniform():
+    n = 7
+    src = np.arange(n, dtype=np.int32)
+    dst = np.roll(src, -1)
+    r, changes = oracle.pagerank(src, dst, n, 0.85, 5)
+    assert np.allclose(r, 1 / n, rtol=0, atol=1e-15) and max(changes) < 1e-15
+
+
+def test_pagerank_star_closed_form():
+    # undirected star, k leaves: at the fixed point r_c = (1 + a k) / (n (1 + a))
+    # and r_leaf = (1 - a)/n + a r_c / k
+    k, a = 9, 0.85
+    n = k + 1
+    leaves = np.arange(1, n, dtype=np.int32)
+    src = np.concatenate([np.zeros(k, np.int32), leaves])
+    dst = np.concatenate([leaves, np.zeros(k, np.int32)])
+    r, changes = oracle.pagerank(src, dst, n, a, 500, tol=1e-13)
+    rc = (1 + a * k) / (n * (1 + a))
+    assert math.isclose(r[0], rc, rel_tol=1e-12)
+    assert np.allclose(r[1:], (1 - a) / n + a * rc / k, rtol=1e-12, atol=0)
+    assert changes[-1] < 1e-13 and all(c >= 1e-13 for c in changes[:-1])  # stopped at the first one below
+
+
+def test_pagerank_is_the_google_matrix_eigenvector():
+    # directed multigraph with dangling vertices: the fixed point is the
+    # eigenvector of eigenvalue 1 of G = a (P + dangling spread) + (1 - a)/n
+    rng = np.random.default_rng(34)
+    n, m, a = 12, 30, 0.8
+    src = rng.integers(0, 8, m).astype(np.int32)   # vertices 8..11 have no out-edges
+    dst = rng.integers(0, n, m).astype(np.int32)
+    G = np.full((n, n), (1 - a) / n)
+    outdeg = np.bincount(src, minlength=n)
+    for u, v in zip(src, dst):
+        G[v, u] += a / outdeg[u]
+    for u in range(n):
+        if outdeg[u] == 0:
+            G[:, u] += a / n
+    w, V = np.linalg.eig(G)
+    vec = np.real(V[:, np.argmin(np.abs(w - 1))])
+    vec /= vec.sum()
+    r, _ = oracle.pagerank(src, dst, n, a, 400)
+    assert np.allclose(r, vec, rtol=1e-10, atol=1e-13)
+    assert math.isclose(r.sum(), 1.0, rel_tol=1e-12)
+
+
+def test_pagerank_without_damping_or_edges():
+    rng = np.random.default_rng(35)
+    src = rng.integers(0, 50, 200).astype(np.int32)
+    dst = rng.integers(0, 50, 200).astype(np.int32)
+    r, _ = oracle.pagerank(src, dst, 50, 0.0, 3)          # damping 0: uniform
+    assert np.allclose(r, 1 / 50, rtol=1e-14, atol=0)
+    r, _ = oracle.pagerank(np.zeros(0, np.int32), np.zeros(0, np.int32), 5, 0.85, 4)  # all dangling
+    assert np.allclose(r, 0.2, rtol=1e-14, atol=0)
