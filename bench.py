@@ -277,6 +277,23 @@ def main():
     stage_ms["reorder"] = float(np.mean([er[k][0].elapsed_time(er[k][1]) for k in range(args.steps)]))
     log(f"boba_reorder alone: {stage_ms['reorder']:.3f} ms")
 
+    # the non-atomic scatter of the paper's GPU kernel (Sec. 4.4): what the
+    # exact minimum costs here, and how much of the order the race changes
+    perm_r, order_r = torch.empty_like(perm), torch.empty_like(order)
+    boba.boba_reorder(src, dst, n, ws=ws_r, perm=perm_r, order=order_r, flags=boba.BOBA_FLAG_RACY)
+    racy_t = []
+    for _ in range(args.steps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record()
+        boba.boba_reorder(src, dst, n, ws=ws_r, perm=perm_r, order=order_r, flags=boba.BOBA_FLAG_RACY)
+        e[1].record()
+        torch.cuda.synchronize()
+        racy_t.append(e[0].elapsed_time(e[1]))
+    racy = {"reorder_ms": float(np.mean(racy_t)), "exact_reorder_ms": stage_ms["reorder"],
+            "same_new_id_fraction": float((perm_r == perm).float().mean())}
+    del order_r
+    log(f"racy scatter: {racy['reorder_ms']:.3f} ms, {racy['same_new_id_fraction']:.4f} of the IDs as exact")
+
     # SpMV and CSR build on the input labelling ("before")
     log("before-reorder leg")
     rp0 = torch.empty(n + 1, dtype=torch.int32, device=dev)
@@ -303,6 +320,23 @@ def main():
 
     # locality of the CSR rows (NBR of Sec. 5.2, 32-ID lines) before and after
     ws_nbr = torch.empty(boba.boba_nbr_workspace(n, m), dtype=torch.uint8, device=dev)
+    # the racy order's quality (NBR, SpMV rate), using the before-leg buffers
+    sr, dr = boba.boba_relabel(src, dst, perm_r)
+    boba.coo_to_csr(sr, dr, val, n, ws=ws_c, out=(rp0, col0, val0))
+    del sr, dr, perm_r
+    racy["nbr_over_nonempty_rows"] = boba.boba_nbr(rp0, col0, n, 32, ws=ws_nbr)[1]
+    rt = []
+    for _ in range(args.before_reps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record()
+        boba.spmv_csr(rp0, col0, val0, x2, y=y0, ws=ws_s)
+        e[1].record()
+        torch.cuda.synchronize()
+        rt.append(e[0].elapsed_time(e[1]))
+    racy["spmv_gflops"] = 2 * m / (float(np.median(rt)) * 1e-3) / 1e9
+    log(f"racy order: NBR {racy['nbr_over_nonempty_rows']:.4f}, SpMV {racy['spmv_gflops']:.1f} GFLOP/s")
+    # the before-leg CSR again, for NBR before
+    boba.coo_to_csr(src, dst, val, n, ws=ws_c, out=(rp0, col0, val0))
     nbr_before = boba.boba_nbr(rp0, col0, n, 32, ws=ws_nbr)
     en = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     en[0].record()
@@ -386,6 +420,7 @@ def main():
         "binned": binned,
         "nbr": nbr,
         "pagerank": pagerank,
+        "racy_scatter": racy,
         "paper_context": PAPER_CONTEXT,
         "device": torch.cuda.get_device_name(0),
         "source_digest": source_digest(),

@@ -47,6 +47,12 @@ typedef int32_t boba_status;
 /* boba_reorder flags */
 #define BOBA_FLAG_INTERLEAVED 0x1u /* flatten as I(0) J(0) I(1) J(1) ... (Fig. 1)
                                       instead of I ++ J (Algorithms 1 and 2) */
+#define BOBA_FLAG_RACY 0x2u        /* plain stores instead of AtomicMin in the
+                                      scatter, as the paper's GPU kernel writes
+                                      r (Sec. 4.4): first(v) becomes some
+                                      position of v, not necessarily the first,
+                                      and may differ from run to run.  For
+                                      measuring what the atomic costs. */
 
 /* Thread-local, NUL-terminated description of the most recent failure on this
  * thread ("" if none).  The string stays valid until the next call. */
@@ -71,7 +77,7 @@ BOBA_API boba_status boba_check_device_error(hipStream_t stream, int32_t *code);
  *   order     int32[n]  output, may be NULL.
  *   ws        workspace of at least boba_reorder_workspace(n, m) bytes,
  *             256-byte aligned; contents on entry are ignored.
- *   flags     0 or BOBA_FLAG_INTERLEAVED.
+ *   flags     0, or BOBA_FLAG_INTERLEAVED and/or BOBA_FLAG_RACY.
  * Errors: BOBA_ERR_ARG, BOBA_ERR_OVERFLOW, BOBA_ERR_WORKSPACE, BOBA_ERR_HIP. */
 BOBA_API size_t boba_reorder_workspace(int64_t n, int64_t m);
 BOBA_API boba_status boba_reorder(const int32_t *src, const int32_t *dst, int64_t m, int64_t n,

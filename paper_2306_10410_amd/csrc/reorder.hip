@@ -44,7 +44,16 @@ __global__ __launch_bounds__(kBlock) void k_reorder_init(uint32_t *__restrict__ 
 // already shows a smaller position: r only decreases, so a stale value is
 // never smaller than the current one and the skip is always safe.  All probe
 // reads of a thread are issued before its first atomic so that they overlap.
-template <int K>
+// RACY: a plain store after the comparison, the non-atomic write of the
+// paper's GPU kernel (Sec. 4.4): r[v] ends up at one of v's positions, not
+// necessarily the first.
+template <bool RACY>
+__device__ __forceinline__ void lower(uint32_t *r, uint32_t pos) {
+    if (RACY) *r = pos;
+    else atomicMin(r, pos);
+}
+
+template <bool RACY, int K>
 __device__ __forceinline__ void visit_all(uint32_t *__restrict__ r, const int32_t (&v)[K], const uint32_t (&pos)[K],
                                           const bool (&live)[K], uint32_t n, int32_t *flag) {
     // Unconditional loads (index clamped to 0 when unused) keep the probes in
@@ -56,24 +65,25 @@ __device__ __forceinline__ void visit_all(uint32_t *__restrict__ r, const int32_
     for (int q = 0; q < K; ++q) {
         if (!live[q]) continue;
         if ((uint32_t)v[q] < n) {
-            if (pos[q] < cur[q]) atomicMin(&r[v[q]], pos[q]);
+            if (pos[q] < cur[q]) lower<RACY>(&r[v[q]], pos[q]);
         } else {
             flag_range_error(flag);
         }
     }
 }
 
+template <bool RACY>
 __device__ __forceinline__ void visit(uint32_t *__restrict__ r, int32_t v, uint32_t pos, uint32_t n,
                                       int32_t *flag) {
     if ((uint32_t)v < n) {
-        if (pos < r[v]) atomicMin(&r[v], pos);
+        if (pos < r[v]) lower<RACY>(&r[v], pos);
     } else {
         flag_range_error(flag);
     }
 }
 
 // Chunk c < m4 covers src[4c .. 4c+3]; chunk c >= m4 covers dst[4(c-m4) .. +3].
-template <bool INTERLEAVED>
+template <bool INTERLEAVED, bool RACY>
 __global__ __launch_bounds__(kBlock) void k_scatter_min_vec(const v4i *__restrict__ src4,
                                                             const v4i *__restrict__ dst4, uint32_t m4,
                                                             uint32_t m, uint32_t n, uint32_t *__restrict__ r,
@@ -104,11 +114,11 @@ __global__ __launch_bounds__(kBlock) void k_scatter_min_vec(const v4i *__restric
             live[4 * u + q] = ok;
         }
     }
-    visit_all(r, v, pos, live, n, flag);
+    visit_all<RACY>(r, v, pos, live, n, flag);
 }
 
 // Edges k in [k0, m): both endpoints, scalar loads (tails and unaligned input).
-template <bool INTERLEAVED>
+template <bool INTERLEAVED, bool RACY>
 __global__ __launch_bounds__(kBlock) void k_scatter_min_scalar(const int32_t *__restrict__ src,
                                                                const int32_t *__restrict__ dst, uint32_t k0,
                                                                uint32_t m, uint32_t n, uint32_t *__restrict__ r,
@@ -119,7 +129,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_min_scalar(const int32_t *__
         const bool is_dst = t >= cnt;
         const uint32_t k = k0 + (uint32_t)(is_dst ? t - cnt : t);
         const uint32_t pos = INTERLEAVED ? 2 * k + (is_dst ? 1 : 0) : (is_dst ? m + k : k);
-        visit(r, is_dst ? dst[k] : src[k], pos, n, flag);
+        visit<RACY>(r, is_dst ? dst[k] : src[k], pos, n, flag);
     }
 }
 
@@ -439,6 +449,7 @@ __global__ __launch_bounds__(256) void k_transpose(const uint32_t *__restrict__ 
 // Workgroup (bucket b, slice s) folds the records of tiles [s*tps, (s+1)*tps)
 // into an LDS copy of r for vertices [b*W, (b+1)*W).  Element k of half h has
 // position hbase[h] + stride * k.
+template <bool RACY>
 __global__ __launch_bounds__(kMinThreads) void k_bucket_min(const uint32_t *__restrict__ recs,
                                                             const uint32_t *__restrict__ off_t, uint32_t nt,
                                                             uint32_t tiles_half, uint32_t region, uint32_t nb,
@@ -466,7 +477,7 @@ __global__ __launch_bounds__(kMinThreads) void k_bucket_min(const uint32_t *__re
         if (rec == kSentinel) return;
         const uint32_t i = rec & (kBucketW - 1);
         const uint32_t p = pb + stride * (rec >> kVBits);
-        if (p < lr[i]) atomicMin(&lr[i], p);
+        if (p < lr[i]) lower<RACY>(&lr[i], p);
     };
     // records [kb, min(kb + kChunk, e1)) of a tile's segment, 8 loads in
     // flight per lane
@@ -1025,8 +1036,8 @@ boba_status check_sizes(int64_t m, int64_t n, bool positions) {
 
 // Launches the reorder; *bucketed tells which scatter path ran.
 boba_status reorder_run(const int32_t *src, const int32_t *dst, uint32_t um, uint32_t un, int32_t *perm,
-                        int32_t *order, bool inter, const ReorderPlan &P, const ReorderLayout &L, int32_t *flag,
-                        hipStream_t stream, bool *bucketed_out) {
+                        int32_t *order, bool inter, bool racy, const ReorderPlan &P, const ReorderLayout &L,
+                        int32_t *flag, hipStream_t stream, bool *bucketed_out) {
     const bool bucketed = P.bucketed && aligned16(src) && aligned16(dst);
     *bucketed_out = bucketed;
     const uint32_t tail = 2 * um;
@@ -1036,9 +1047,14 @@ boba_status reorder_run(const int32_t *src, const int32_t *dst, uint32_t um, uin
                     P.tiles_half, un, P.nb, P.region, L.recs, L.tile_off, flag);
         BOBA_LAUNCH("bucket_transpose", k_transpose, dim3(ceil_div(P.nb + 1, 32), ceil_div(P.nt, 32)), dim3(256),
                     stream, (const uint32_t *)L.tile_off, P.nt, P.nb + 1, L.off_t);
-        BOBA_LAUNCH("bucket_min", k_bucket_min, dim3(P.nb * P.slices), dim3(kMinThreads), stream,
-                    (const uint32_t *)L.recs, (const uint32_t *)L.off_t, P.nt, P.tiles_half, P.region, P.nb, P.tps,
-                    min_batch(P), un, inter ? 1u : um, inter ? 2u : 1u, L.r);
+        if (racy)
+            BOBA_LAUNCH("bucket_min", k_bucket_min<true>, dim3(P.nb * P.slices), dim3(kMinThreads), stream,
+                        (const uint32_t *)L.recs, (const uint32_t *)L.off_t, P.nt, P.tiles_half, P.region, P.nb,
+                        P.tps, min_batch(P), un, inter ? 1u : um, inter ? 2u : 1u, L.r);
+        else
+            BOBA_LAUNCH("bucket_min", k_bucket_min<false>, dim3(P.nb * P.slices), dim3(kMinThreads), stream,
+                        (const uint32_t *)L.recs, (const uint32_t *)L.off_t, P.nt, P.tiles_half, P.region, P.nb,
+                        P.tps, min_batch(P), un, inter ? 1u : um, inter ? 2u : 1u, L.r);
         const uint32_t kcols = P.nblk + 1;  // key blocks and the tail block
         BOBA_LAUNCH("rank_count", k_rank_count, dim3(P.nb), dim3(kMinThreads), stream, (const uint32_t *)L.r,
                     P.slices, un, P.nb, P.nblk, P.kbits, L.cnt_b, L.cnt);
@@ -1072,23 +1088,36 @@ boba_status reorder_run(const int32_t *src, const int32_t *dst, uint32_t um, uin
             const uint32_t m4 = um / 4;
             if (m4 > 0) {
                 dim3 grid(ceil_div(2ull * m4, kScatterTile));
-                if (inter)
-                    BOBA_LAUNCH("scatter_min", k_scatter_min_vec<true>, grid, dim3(kBlock), stream,
-                                (const v4i *)src, (const v4i *)dst, m4, um, un, L.r, flag);
+                const v4i *s4 = (const v4i *)src, *d4 = (const v4i *)dst;
+                if (inter && racy)
+                    BOBA_LAUNCH("scatter_min", (k_scatter_min_vec<true, true>), grid, dim3(kBlock), stream, s4, d4,
+                                m4, um, un, L.r, flag);
+                else if (inter)
+                    BOBA_LAUNCH("scatter_min", (k_scatter_min_vec<true, false>), grid, dim3(kBlock), stream, s4, d4,
+                                m4, um, un, L.r, flag);
+                else if (racy)
+                    BOBA_LAUNCH("scatter_min", (k_scatter_min_vec<false, true>), grid, dim3(kBlock), stream, s4, d4,
+                                m4, um, un, L.r, flag);
                 else
-                    BOBA_LAUNCH("scatter_min", k_scatter_min_vec<false>, grid, dim3(kBlock), stream,
-                                (const v4i *)src, (const v4i *)dst, m4, um, un, L.r, flag);
+                    BOBA_LAUNCH("scatter_min", (k_scatter_min_vec<false, false>), grid, dim3(kBlock), stream, s4, d4,
+                                m4, um, un, L.r, flag);
             }
             k0 = 4 * m4;
         }
         if (k0 < um) {
             dim3 grid(grid_for(2ull * (um - k0), kBlock));
-            if (inter)
-                BOBA_LAUNCH("scatter_min_scalar", k_scatter_min_scalar<true>, grid, dim3(kBlock), stream, src, dst,
-                            k0, um, un, L.r, flag);
+            if (inter && racy)
+                BOBA_LAUNCH("scatter_min_scalar", (k_scatter_min_scalar<true, true>), grid, dim3(kBlock), stream,
+                            src, dst, k0, um, un, L.r, flag);
+            else if (inter)
+                BOBA_LAUNCH("scatter_min_scalar", (k_scatter_min_scalar<true, false>), grid, dim3(kBlock), stream,
+                            src, dst, k0, um, un, L.r, flag);
+            else if (racy)
+                BOBA_LAUNCH("scatter_min_scalar", (k_scatter_min_scalar<false, true>), grid, dim3(kBlock), stream,
+                            src, dst, k0, um, un, L.r, flag);
             else
-                BOBA_LAUNCH("scatter_min_scalar", k_scatter_min_scalar<false>, grid, dim3(kBlock), stream, src, dst,
-                            k0, um, un, L.r, flag);
+                BOBA_LAUNCH("scatter_min_scalar", (k_scatter_min_scalar<false, false>), grid, dim3(kBlock), stream,
+                            src, dst, k0, um, un, L.r, flag);
         }
         BOBA_LAUNCH("mark", k_mark, dim3(grid_for(un, kBlock * 4)), dim3(kBlock), stream, (const uint32_t *)L.r, un,
                     tail, L.W);
@@ -1122,7 +1151,8 @@ boba_status relabel_run(const int32_t *src, const int32_t *dst, uint32_t um, con
 boba_status reorder_args(const int32_t *src, const int32_t *dst, int64_t m, int64_t n, int32_t *perm, uint32_t flags,
                          const char *who) {
     if (boba_status e = check_sizes(m, n, true)) return e;
-    if (flags & ~BOBA_FLAG_INTERLEAVED) return fail(BOBA_ERR_ARG, "%s: unknown flags 0x%x", who, flags);
+    if (flags & ~(BOBA_FLAG_INTERLEAVED | BOBA_FLAG_RACY))
+        return fail(BOBA_ERR_ARG, "%s: unknown flags 0x%x", who, flags);
     if (m > 0 && (!src || !dst)) return fail(BOBA_ERR_ARG, "%s: src/dst is NULL", who);
     if (m > 0 && n == 0) return fail(BOBA_ERR_ARG, "%s: edges given but n = 0", who);
     if (n > 0 && !perm) return fail(BOBA_ERR_ARG, "%s: perm is NULL", who);
@@ -1153,7 +1183,8 @@ extern "C" boba_status boba_reorder(const int32_t *src, const int32_t *dst, int6
     const ReorderPlan P = reorder_plan(n, m);
     const ReorderLayout L = reorder_layout(ws, n, m, P);
     bool bucketed = false;
-    return reorder_run(src, dst, (uint32_t)m, (uint32_t)n, perm, order, flags & BOBA_FLAG_INTERLEAVED, P, L, flag,
+    return reorder_run(src, dst, (uint32_t)m, (uint32_t)n, perm, order, flags & BOBA_FLAG_INTERLEAVED,
+                       flags & BOBA_FLAG_RACY, P, L, flag,
                        stream, &bucketed);
 }
 
@@ -1180,7 +1211,8 @@ extern "C" boba_status boba_reorder_relabel(const int32_t *src, const int32_t *d
     const ReorderPlan P = reorder_plan(n, m);
     const ReorderLayout L = reorder_layout(ws, n, m, P, true);
     bool bucketed = false;
-    if (boba_status e = reorder_run(src, dst, um, un, perm, order, flags & BOBA_FLAG_INTERLEAVED, P, L, flag, stream,
+    if (boba_status e = reorder_run(src, dst, um, un, perm, order, flags & BOBA_FLAG_INTERLEAVED,
+                                    flags & BOBA_FLAG_RACY, P, L, flag, stream,
                                     &bucketed))
         return e;
     if (m == 0) return BOBA_OK;

@@ -330,3 +330,65 @@ def test_sorted_inputs_long_segments(case):
     src = rng.integers(0, n, m).astype(np.int32)
     g = graphgen.Graph(case, n, src, dst)
     full_path_check(g, boba, interleaved=case == "dst_sorted", check_spmv=False)
+
+
+def racy_result_is_valid(src, dst, n, perm, order, interleaved=False):
+    """What the non-atomic scatter still guarantees: perm is a permutation with
+    inverse order, vertices that never occur come last in increasing ID, and
+    the others are ordered by positions at which they occur (greedy: each
+    takes its first position after the previous vertex's)."""
+    m = src.size
+    S = np.empty(2 * m, np.int64)
+    if interleaved:
+        S[0::2], S[1::2] = src, dst
+    else:
+        S[:m], S[m:] = src, dst
+    assert np.array_equal(np.sort(perm), np.arange(n)) and np.array_equal(order[perm], np.arange(n))
+    occurs = np.zeros(n, bool)
+    occurs[S] = True
+    k = int(occurs.sum())
+    assert np.all(occurs[order[:k]]) and np.array_equal(order[k:], np.flatnonzero(~occurs))
+    pos = np.argsort(S, kind="stable")                      # positions grouped by vertex, increasing
+    start = np.concatenate([[0], np.cumsum(np.bincount(S, minlength=n))])
+    cursor = -1
+    for v in order[:k]:
+        p = pos[start[v]:start[v + 1]]
+        j = np.searchsorted(p, cursor, side="right")
+        if j == p.size:
+            return False
+        cursor = p[j]
+    return True
+
+
+@pytest.mark.parametrize("kind,n,m,interleaved", [("rmat", 1 << 16, 1 << 20, False), ("uniform", 70001, 300007, True),
+                                                  ("rmat", (1 << 20) + 3, 1 << 22, False)])
+def test_racy_flag_gives_a_valid_order(kind, n, m, interleaved):
+    g = graphgen.small_workload(kind, n, m, 106 + n % 11)
+    flags = boba.BOBA_FLAG_RACY | (boba.BOBA_FLAG_INTERLEAVED if interleaved else 0)
+    perm, order = boba.boba_reorder(dev(g.src), dev(g.dst), g.n, flags=flags)
+    assert racy_result_is_valid(g.src, g.dst, g.n, host(perm), host(order), interleaved)
+    # the fused call relabels with its own permutation
+    fp, fo, fs, fd = boba.boba_reorder_relabel(dev(g.src), dev(g.dst), g.n, flags=flags)
+    fp_h = host(fp)
+    assert racy_result_is_valid(g.src, g.dst, g.n, fp_h, host(fo), interleaved)
+    assert np.array_equal(host(fs), fp_h[g.src]) and np.array_equal(host(fd), fp_h[g.dst])
+
+
+def test_racy_flag_is_exact_when_every_vertex_occurs_once():
+    # no two positions hold the same vertex, so there is no race to lose
+    rng = np.random.default_rng(107)
+    m = 150001
+    n = 2 * m + 999
+    ids = rng.permutation(n)[: 2 * m].astype(np.int32)
+    src, dst = ids[:m].copy(), ids[m:].copy()
+    for flags in (boba.BOBA_FLAG_RACY, boba.BOBA_FLAG_RACY | boba.BOBA_FLAG_INTERLEAVED):
+        perm, order = boba.boba_reorder(dev(src), dev(dst), n, flags=flags)
+        p_ref, o_ref = oracle.boba(src, dst, n, interleaved=bool(flags & boba.BOBA_FLAG_INTERLEAVED))
+        assert np.array_equal(host(perm), p_ref) and np.array_equal(host(order), o_ref)
+
+
+def test_racy_flag_on_the_direct_path():
+    n, m = (1 << 25) + 7, 1 << 18
+    src, dst = graphgen.uniform_edges(n, m, 108)
+    perm, order = boba.boba_reorder(dev(src), dev(dst), n, flags=boba.BOBA_FLAG_RACY)
+    assert racy_result_is_valid(src, dst, n, host(perm), host(order))
