@@ -713,6 +713,7 @@ __global__ __launch_bounds__(kSplitThreads) void k_tile_unsplit(const uint32_t *
 //                 isolated vertices take the tail ranks in increasing ID
 // Every step streams or works in LDS: no device-wide random atomics.
 constexpr uint32_t kMinKeyBits = 15;
+constexpr uint32_t kPermChunk = 1024;  // key blocks rank_perm takes at a time (= its threads)
 constexpr uint32_t kMaxKeyBits = 18;                            // rank_block LDS <= 48 KB
 constexpr uint32_t kTargetKeyBlocks = 4096;                    // bounds a key block's entries
 constexpr uint32_t kMaxKeyBlocks = 1u << (32 - kMaxKeyBits);    // 2m < 2^32
@@ -787,17 +788,17 @@ inline size_t rank_block_lds(uint32_t kbits) {
     return words * 4 + words * 2 + (words / kWave) * 4;
 }
 
-__global__ __launch_bounds__(kRankThreads) void k_rank_block(const uint2 *__restrict__ E,
+__global__ __launch_bounds__(kRankThreads) void k_rank_block(uint2 *__restrict__ E,
                                                              const uint32_t *__restrict__ off, uint32_t nb,
-                                                             uint32_t kbits, uint32_t *__restrict__ Rk,
-                                                             int32_t *__restrict__ order) {
+                                                             uint32_t kbits, int32_t *__restrict__ order) {
     extern __shared__ __align__(16) uint32_t dyn[];
     const uint32_t nwords = 1u << (kbits - 5);
     const uint32_t ngroups = nwords / kWave;  // 16 .. 256
     uint32_t *bits = dyn;
     uint16_t *pre = (uint16_t *)(dyn + nwords);      // exclusive popcount within a 64-word group
     uint32_t *gbase = dyn + nwords + nwords / 2;     // exclusive popcount of the groups
-    const uint32_t blk = xcd_work_index(blockIdx.x, gridDim.x);
+    // plain order: the dense first key blocks go round-robin to all XCDs
+    const uint32_t blk = blockIdx.x;
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = threadIdx.x / kWave;
     constexpr uint32_t NWAVE = kRankThreads / kWave;
@@ -807,16 +808,33 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_block(const uint2 *__rest
     const uint32_t e1 = off[(size_t)(blk + 1) * nb];
     const uint32_t base = blk << kbits;
     constexpr int U = 8;  // entries in flight per thread
-    for (uint32_t e = e0 + threadIdx.x; e < e1; e += U * kRankThreads) {
-        uint32_t p[U];
+    // a block of at most U * kRankThreads entries (nearly all) stays in
+    // registers between setting the bits and ranking
+    const bool one_pass = e1 - e0 <= U * kRankThreads;
+    uint2 held[U];
+    if (one_pass) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const uint32_t i = e + u * kRankThreads;
-            p[u] = i < e1 ? E[i].x - base : 0u;
+            const uint32_t i = e0 + threadIdx.x + u * kRankThreads;
+            held[u] = i < e1 ? E[i] : make_uint2(base, 0u);
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (e + u * kRankThreads < e1) atomicOr(&bits[p[u] >> 5], 1u << (p[u] & 31));
+        for (int u = 0; u < U; ++u) {
+            const uint32_t p = held[u].x - base;
+            if (e0 + threadIdx.x + u * kRankThreads < e1) atomicOr(&bits[p >> 5], 1u << (p & 31));
+        }
+    } else {
+        for (uint32_t e = e0 + threadIdx.x; e < e1; e += U * kRankThreads) {
+            uint32_t p[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t i = e + u * kRankThreads;
+                p[u] = i < e1 ? E[i].x - base : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (e + u * kRankThreads < e1) atomicOr(&bits[p[u] >> 5], 1u << (p[u] & 31));
+        }
     }
     __syncthreads();
     for (uint32_t g = wave; g < ngroups; g += NWAVE) {
@@ -850,7 +868,7 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_block(const uint2 *__rest
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint32_t i = e + u * kRankThreads;
-            x[u] = i < e1 ? E[i] : make_uint2(base, 0u);
+            x[u] = one_pass ? held[u] : (i < e1 ? E[i] : make_uint2(base, 0u));
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -858,7 +876,7 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_block(const uint2 *__rest
             const uint32_t p = x[u].x - base;
             const uint32_t w = p >> 5;
             const uint32_t k = e0 + gbase[w / kWave] + pre[w] + __popc(bits[w] & ((1u << (p & 31)) - 1u));
-            Rk[e + u * kRankThreads] = k;  // beside the entry (coalesced)
+            E[e + u * kRankThreads] = make_uint2(k, x[u].y);  // the rank replaces the key (coalesced)
             if (order) order[k] = (int32_t)x[u].y;  // within the block's rank range
         }
     }
@@ -869,12 +887,14 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_block(const uint2 *__rest
 // entries of 8 segments in flight); isolated vertices (still unset) take the
 // tail ranks from iso_base on in increasing ID, via one ballot bitmap and one
 // scan; the slice is written out coalesced.
-__global__ __launch_bounds__(kMinThreads) void k_rank_perm(const uint2 *__restrict__ E, const uint32_t *__restrict__ Rk,
+__global__ __launch_bounds__(kMinThreads) void k_rank_perm(const uint2 *__restrict__ E,
                                                            const uint32_t *__restrict__ off_b,
                                                            const uint32_t *__restrict__ cnt_b, uint32_t nblk,
                                                            uint32_t n, int32_t *__restrict__ perm,
                                                            int32_t *__restrict__ order) {
     __shared__ uint32_t lp[kBucketW];
+    __shared__ uint32_t pre[kPermChunk + 1];  // entries of the bucket in earlier key blocks of the chunk
+    __shared__ uint32_t obs[kPermChunk];      // where the bucket's slice of each key block starts in E
     __shared__ uint32_t flags[kBucketW / 32];
     __shared__ uint32_t scan_lds[kMinThreads / kWave];
     const uint32_t b = blockIdx.x;
@@ -882,40 +902,52 @@ __global__ __launch_bounds__(kMinThreads) void k_rank_perm(const uint2 *__restri
     const uint32_t cntv = min(kBucketW, n - v0);
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = threadIdx.x / kWave;
-    constexpr uint32_t NWAVE = kMinThreads / kWave;
     for (uint32_t i = threadIdx.x; i < kBucketW; i += kMinThreads) lp[i] = kInf;
-    __syncthreads();
-    constexpr int U = 8;
     const uint32_t *ob = off_b + (size_t)b * (nblk + 1);
     const uint32_t *cb = cnt_b + (size_t)b * (nblk + 1);
-    for (uint32_t g = wave * kWave; g < nblk; g += NWAVE * kWave) {
-        const uint32_t my = g + lane;
-        const uint32_t sb = my < nblk ? ob[my] : 0u;
-        const uint32_t se = my < nblk ? sb + cb[my] : 0u;
-        const uint32_t cnt = min((uint32_t)kWave, nblk - g);
-        for (uint32_t j0 = 0; j0 < cnt; j0 += U) {
-            uint32_t vv[U], rk[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t j = j0 + u;
-                const uint32_t b0 = __shfl(sb, j & (kWave - 1), kWave);
-                const uint32_t e0 = __shfl(se, j & (kWave - 1), kWave);
-                const uint32_t e = b0 + lane;
-                const bool ok = j < cnt && e < e0;
-                vv[u] = ok ? E[e].y : kInf;
-                rk[u] = ok ? Rk[e] : 0u;
+    // The bucket's entries lie in one small slice per key block.  Per chunk of
+    // kPermChunk key blocks, the slices are numbered through in order and each
+    // thread takes a contiguous run of them, 8 loads in flight.
+    constexpr int U = 8;
+    for (uint32_t k0 = 0; k0 < nblk; k0 += kPermChunk) {
+        const uint32_t kc = min(kPermChunk, nblk - k0);
+        const uint32_t t = threadIdx.x;
+        const uint32_t c = t < kc ? cb[k0 + t] : 0u;
+        if (t < kc) obs[t] = ob[k0 + t];
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan<kMinThreads>(c, OpSum{}, scan_lds, tot);
+        pre[t] = ex;  // = tot for t >= kc
+        if (t == 0) pre[kPermChunk] = tot;
+        __syncthreads();
+        const uint32_t per = (tot + kMinThreads - 1) / kMinThreads;
+        uint32_t i = t * per;
+        const uint32_t iend = min(tot, i + per);
+        if (i < iend) {
+            uint32_t k = 0, hi = kc - 1;  // the last slice starting at or before entry i
+            while (k < hi) {
+                const uint32_t mid = (k + hi + 1) >> 1;
+                if (pre[mid] <= i) k = mid;
+                else hi = mid - 1;
             }
+            for (; i < iend; i += U) {
+                uint2 x[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (vv[u] != kInf) lp[(vv[u] - v0) & (kBucketW - 1)] = rk[u];
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t ii = i + u;
+                    if (ii < iend) {
+                        while (pre[k + 1] <= ii) ++k;
+                        x[u] = E[obs[k] + (ii - pre[k])];
+                    } else {
+                        x[u] = make_uint2(0u, kInf);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (x[u].y != kInf) lp[(x[u].y - v0) & (kBucketW - 1)] = x[u].x;
+            }
         }
-        for (uint32_t j = 0; j < cnt; ++j) {  // entries beyond the first 64 (dense key blocks)
-            const uint32_t b0 = __shfl(sb, j, kWave);
-            const uint32_t e0 = __shfl(se, j, kWave);
-            for (uint32_t e = b0 + kWave + lane; e < e0; e += kWave) lp[(E[e].y - v0) & (kBucketW - 1)] = Rk[e];
-        }
+        __syncthreads();  // pre and obs are rewritten by the next chunk
     }
-    __syncthreads();
     // isolated flags: vertices [u*1024 + wave*64, +64) -> words 32u + 2 wave, +1
     for (uint32_t u = 0; u < kBucketW / kMinThreads; ++u) {
         const uint32_t i = u * kMinThreads + threadIdx.x;
@@ -988,7 +1020,7 @@ struct ReorderLayout {
     uint32_t *partial;
     uint32_t *recs, *tile_off, *off_t;
     uint32_t *vals;  // new IDs in record layout (fused relabel only)
-    uint32_t *cnt, *cnt_b, *off_b, *cnt_partial, *Rk;  // bucketed ranking
+    uint32_t *cnt, *cnt_b, *off_b, *cnt_partial;  // bucketed ranking
     uint2 *E;
     uint32_t ncnt;
     size_t bytes;
@@ -1013,7 +1045,6 @@ ReorderLayout reorder_layout(void *ws, int64_t n, int64_t m, const ReorderPlan &
     L.off_b = c.take<uint32_t>(P.bucketed ? L.ncnt - 1 : 0);
     L.cnt_partial = c.take<uint32_t>(P.bucketed ? scan_partials(L.ncnt) : 0);
     L.E = c.take<uint2>(P.bucketed ? (size_t)n : 0);
-    L.Rk = c.take<uint32_t>(P.bucketed ? (size_t)n : 0);
     L.bytes = c.bytes();
     return L;
 }
@@ -1071,14 +1102,13 @@ boba_status reorder_run(const int32_t *src, const int32_t *dst, uint32_t um, uin
         {
             const size_t lds = rank_block_lds(P.kbits);
             const int tok = timing_begin("rank_block", stream);
-            hipLaunchKernelGGL(k_rank_block, dim3(P.nblk), dim3(kRankThreads), lds, stream, (const uint2 *)L.E,
-                               (const uint32_t *)L.cnt, P.nb, P.kbits, L.Rk, order);
+            hipLaunchKernelGGL(k_rank_block, dim3(P.nblk), dim3(kRankThreads), lds, stream, L.E,
+                               (const uint32_t *)L.cnt, P.nb, P.kbits, order);
             timing_end(tok, stream);
             if (boba_status e = check_launch("rank_block")) return e;
         }
         BOBA_LAUNCH("rank_perm", k_rank_perm, dim3(P.nb), dim3(kMinThreads), stream, (const uint2 *)L.E,
-                    (const uint32_t *)L.Rk, (const uint32_t *)L.off_b, (const uint32_t *)L.cnt_b, P.nblk, un, perm,
-                    order);
+                    (const uint32_t *)L.off_b, (const uint32_t *)L.cnt_b, P.nblk, un, perm, order);
         return BOBA_OK;
     } else {
         BOBA_LAUNCH("reorder_init", k_reorder_init, dim3(grid_for(un > L.nw ? un : L.nw, kBlock * 4)),
