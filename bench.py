@@ -440,15 +440,18 @@ def bench_pagerank(src, dst, s2, d2, perm, n, m, dev, ws_c, iters=20, reps=3):
     colT = torch.empty(m, dtype=torch.int32, device=dev)
     ws = torch.empty(boba.boba_pagerank_workspace(n, m), dtype=torch.uint8, device=dev)
     out, ranks = {"iters": iters, "damping": 0.85}, {}
+    rpF = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    colF = torch.empty(m, dtype=torch.int32, device=dev)
     for name, (a, b) in (("before", (src, dst)), ("after", (s2, d2))):
+        boba.coo_to_csr(a, b, None, n, ws=ws_c, out=(rpF, colF, None))  # forward: out-degrees
         boba.coo_to_csr(b, a, None, n, ws=ws_c, out=(rpT, colT, None))  # row v: sources of edges into v
         rank = torch.empty(n, dtype=torch.float32, device=dev)
-        boba.boba_pagerank(rpT, colT, 0.85, iters, rank=rank, ws=ws)
+        boba.boba_pagerank(rpT, colT, 0.85, iters, out_rowptr=rpF, rank=rank, ws=ws)
         times = []
         for _ in range(reps):
             e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
             e[0].record()
-            boba.boba_pagerank(rpT, colT, 0.85, iters, rank=rank, ws=ws)
+            boba.boba_pagerank(rpT, colT, 0.85, iters, out_rowptr=rpF, rank=rank, ws=ws)
             e[1].record()
             torch.cuda.synchronize()
             times.append(e[0].elapsed_time(e[1]))

@@ -38,7 +38,8 @@ PROTOTYPES = {
     "spmv_csr_workspace": (_SZ, [_I64, _I64]),
     "spmv_csr": (_I32, [_P, _P, _P, _I64, _I64, _I64, _P, _P, _P, _SZ, _P]),
     "boba_pagerank_workspace": (_SZ, [_I64, _I64]),
-    "boba_pagerank": (_I32, [_P, _P, _I64, _I64, ctypes.c_float, _I32, ctypes.c_double, _P, _P, _P, _P, _SZ, _P]),
+    "boba_pagerank": (_I32, [_P, _P, _P, _I64, _I64, ctypes.c_float, _I32, ctypes.c_double, _P, _P, _P, _P, _SZ,
+                             _P]),
     "boba_nbr_workspace": (_SZ, [_I64, _I64]),
     "boba_nbr": (_I32, [_P, _P, _I64, _I64, _I64, _I32, _P, _P, _P, _SZ, _P]),
     "boba_batch_workspace": (_SZ, [_I32, _P, _P, _P]),
@@ -226,22 +227,27 @@ def boba_pagerank_workspace(n: int, nnz: int) -> int:
     return int(load().boba_pagerank_workspace(n, nnz))
 
 
-def boba_pagerank(rowptr, col, damping: float = 0.85, max_iter: int = 20, tol: float = 0.0, *, rank=None,
-                  ws=None, stream=None):
+def boba_pagerank(rowptr, col, damping: float = 0.85, max_iter: int = 20, tol: float = 0.0, *, out_rowptr=None,
+                  rank=None, ws=None, stream=None):
     """PageRank over the transposed CSR (row v lists the sources of the edges
-    into v).  Returns (rank float32[n], residual float64[max_iter], iters
-    int32[1]), all device tensors; residual entries past iters are unset."""
+    into v); out_rowptr, the forward CSR's row pointer, gives the out-degrees
+    without atomics.  Returns (rank float32[n], residual float64[max_iter],
+    iters int32[1]), all device tensors; residual entries past iters are unset."""
     _dev_i32(rowptr, "rowptr")
     _dev_i32(col, "col")
+    if out_rowptr is not None:
+        _dev_i32(out_rowptr, "out_rowptr")
+        if out_rowptr.numel() != rowptr.numel():
+            raise ValueError("out_rowptr and rowptr differ in length")
     n = rowptr.numel() - 1
     dev = rowptr.device
     rank = torch.empty(max(n, 0), dtype=torch.float32, device=dev) if rank is None else rank
     residual = torch.full((max(max_iter, 0),), float("nan"), dtype=torch.float64, device=dev)
     iters = torch.zeros(1, dtype=torch.int32, device=dev)
     ws = _workspace(boba_pagerank_workspace(n, col.numel()), dev, ws)
-    _check(load().boba_pagerank(_ptr(rowptr), _ptr(col), n, col.numel(), damping, max_iter, tol, _ptr(rank),
-                                _ptr(residual) if max_iter > 0 else None, _ptr(iters), _ptr(ws), ws.numel(),
-                                _stream(stream)))
+    _check(load().boba_pagerank(_ptr(rowptr), _ptr(col), _ptr(out_rowptr), n, col.numel(), damping, max_iter, tol,
+                                _ptr(rank), _ptr(residual) if max_iter > 0 else None, _ptr(iters), _ptr(ws),
+                                ws.numel(), _stream(stream)))
     return rank, residual, iters
 
 

@@ -200,6 +200,17 @@ __global__ __launch_bounds__(kThreads) void k_pr_init(uint32_t n, float *__restr
     }
 }
 
+// Out-degrees from the forward graph's row pointer (one coalesced pass).
+__global__ __launch_bounds__(kThreads) void k_pr_outdeg_rowptr(const int32_t *__restrict__ out_rowptr, uint32_t n,
+                                                               uint32_t nnz, uint32_t *__restrict__ outdeg) {
+    const uint32_t stride = gridDim.x * kThreads;
+    for (uint32_t u = blockIdx.x * kThreads + threadIdx.x; u < n; u += stride) {
+        const int32_t a = out_rowptr[u], b = out_rowptr[u + 1];
+        outdeg[u] = b > a ? min((uint32_t)(b - a), nnz) : 0u;
+    }
+}
+
+// Out-degrees counted from the transposed graph's columns (one atomic per edge).
 __global__ __launch_bounds__(kThreads) void k_pr_outdeg(const int32_t *__restrict__ col, uint32_t nnz, uint32_t n,
                                                         uint32_t *__restrict__ outdeg, int32_t *flag) {
     const uint32_t stride = gridDim.x * kThreads;
@@ -391,9 +402,10 @@ extern "C" size_t boba_pagerank_workspace(int64_t n, int64_t nnz) {
     return pr_layout(nullptr, n, nnz).bytes;
 }
 
-extern "C" boba_status boba_pagerank(const int32_t *rowptr, const int32_t *col, int64_t n, int64_t nnz,
-                                     float damping, int32_t max_iter, double tol, float *rank, double *residual,
-                                     int32_t *iters, void *ws, size_t ws_bytes, hipStream_t stream) {
+extern "C" boba_status boba_pagerank(const int32_t *rowptr, const int32_t *col, const int32_t *out_rowptr,
+                                     int64_t n, int64_t nnz, float damping, int32_t max_iter, double tol,
+                                     float *rank, double *residual, int32_t *iters, void *ws, size_t ws_bytes,
+                                     hipStream_t stream) {
     clear_error();
     if (n < 0 || nnz < 0) return fail(BOBA_ERR_ARG, "boba_pagerank: negative size");
     if (n >= (1ll << 31) || nnz >= (1ll << 31)) return fail(BOBA_ERR_OVERFLOW, "boba_pagerank: sizes must be < 2^31");
@@ -417,8 +429,12 @@ extern "C" boba_status boba_pagerank(const int32_t *rowptr, const int32_t *col, 
     BOBA_LAUNCH("pr_init", k_pr_init, dim3(grid_for(un, kThreads * 4)), dim3(kThreads), stream, un, rank, L.outdeg,
                 L.state);
     if (ue > 0) {
-        BOBA_LAUNCH("pr_outdeg", k_pr_outdeg, dim3(grid_for(ue, kThreads * 4)), dim3(kThreads), stream, col, ue, un,
-                    L.outdeg, flag);
+        if (out_rowptr)
+            BOBA_LAUNCH("pr_outdeg", k_pr_outdeg_rowptr, dim3(grid_for(un, kThreads * 4)), dim3(kThreads), stream,
+                        out_rowptr, un, ue, L.outdeg);
+        else
+            BOBA_LAUNCH("pr_outdeg", k_pr_outdeg, dim3(grid_for(ue, kThreads * 4)), dim3(kThreads), stream, col, ue,
+                        un, L.outdeg, flag);
         BOBA_LAUNCH("spmv_split", k_spmv_split, dim3(ceil_div(S.nchunk + 1ull, kThreads)), dim3(kThreads), stream,
                     rowptr, un, (int32_t)ue, S.nchunk, S.split_i, S.split_j);
     }

@@ -153,16 +153,16 @@ def test_pagerank_argument_errors(lib):
     assert need > 0 and lib.boba_pagerank_workspace(5, -1) == 0
     A, B, R = FAKE, P(0x10100), P(0x10200)
     for damping in (-0.1, 1.5, float("nan")):
-        assert lib.boba_pagerank(A, B, 5, 9, damping, 3, 0.0, R, None, None, A, need, None) == boba.BOBA_ERR_ARG
-    assert lib.boba_pagerank(A, B, 5, 9, 0.85, -1, 0.0, R, None, None, A, need, None) == boba.BOBA_ERR_ARG
-    assert lib.boba_pagerank(A, B, 5, 9, 0.85, 3, -1e-3, R, None, None, A, need, None) == boba.BOBA_ERR_ARG
-    assert lib.boba_pagerank(A, B, 5, 9, 0.85, 3, float("nan"), R, None, None, A, need, None) == boba.BOBA_ERR_ARG
-    assert lib.boba_pagerank(None, B, 5, 9, 0.85, 3, 0.0, R, None, None, A, need, None) == boba.BOBA_ERR_ARG
-    assert lib.boba_pagerank(A, None, 5, 9, 0.85, 3, 0.0, R, None, None, A, need, None) == boba.BOBA_ERR_ARG
-    assert lib.boba_pagerank(A, B, 5, 9, 0.85, 3, 0.0, None, None, None, A, need, None) == boba.BOBA_ERR_ARG
-    assert lib.boba_pagerank(A, B, 1 << 31, 9, 0.85, 3, 0.0, R, None, None, A, need, None) == boba.BOBA_ERR_OVERFLOW
-    assert lib.boba_pagerank(A, B, 5, 9, 0.85, 3, 0.0, R, None, None, A, need - 1, None) == boba.BOBA_ERR_WORKSPACE
-    assert lib.boba_pagerank(None, None, 0, 0, 0.85, 3, 0.0, None, None, None, None, 0, None) == boba.BOBA_OK
+        assert lib.boba_pagerank(A, B, None, 5, 9, damping, 3, 0.0, R, None, None, A, need, None) == boba.BOBA_ERR_ARG
+    assert lib.boba_pagerank(A, B, None, 5, 9, 0.85, -1, 0.0, R, None, None, A, need, None) == boba.BOBA_ERR_ARG
+    assert lib.boba_pagerank(A, B, None, 5, 9, 0.85, 3, -1e-3, R, None, None, A, need, None) == boba.BOBA_ERR_ARG
+    assert lib.boba_pagerank(A, B, None, 5, 9, 0.85, 3, float("nan"), R, None, None, A, need, None) == boba.BOBA_ERR_ARG
+    assert lib.boba_pagerank(None, B, None, 5, 9, 0.85, 3, 0.0, R, None, None, A, need, None) == boba.BOBA_ERR_ARG
+    assert lib.boba_pagerank(A, None, None, 5, 9, 0.85, 3, 0.0, R, None, None, A, need, None) == boba.BOBA_ERR_ARG
+    assert lib.boba_pagerank(A, B, None, 5, 9, 0.85, 3, 0.0, None, None, None, A, need, None) == boba.BOBA_ERR_ARG
+    assert lib.boba_pagerank(A, B, None, 1 << 31, 9, 0.85, 3, 0.0, R, None, None, A, need, None) == boba.BOBA_ERR_OVERFLOW
+    assert lib.boba_pagerank(A, B, None, 5, 9, 0.85, 3, 0.0, R, None, None, A, need - 1, None) == boba.BOBA_ERR_WORKSPACE
+    assert lib.boba_pagerank(None, None, None, 0, 0, 0.85, 3, 0.0, None, None, None, None, 0, None) == boba.BOBA_OK
 
 
 def test_binding_refuses_host_tensors():

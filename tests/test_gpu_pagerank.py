@@ -33,6 +33,10 @@ def transposed_csr(src, dst, n):
 def pr_check(src, dst, n, damping=0.85, iters=20):
     rowptr, col = transposed_csr(src, dst, n)
     rank, res, it = boba.boba_pagerank(dev(rowptr), dev(col), damping, iters)
+    # out-degrees from the forward CSR's row pointer instead of atomics: the same bits
+    fwd_rowptr, _, _ = oracle.coo_to_csr(src, dst, None, n)
+    rank2, _, _ = boba.boba_pagerank(dev(rowptr), dev(col), damping, iters, out_rowptr=dev(fwd_rowptr))
+    assert np.array_equal(host(rank2).view(np.uint32), host(rank).view(np.uint32))
     r_ref, ch_ref = oracle.pagerank(src, dst, n, damping, iters)
     rank_h = host(rank).astype(np.float64)
     bound = l1_bound(damping, max(iters, 1))
