@@ -152,6 +152,9 @@ def main():
     ap.add_argument("--bin-bits", type=int, default=8,
                     help="also time binning the edges by destination into 2^B bins before BOBA (0: skip)")
     ap.add_argument("--shuffle-edges", action="store_true", help="put the workload's edges in random order first")
+    ap.add_argument("--cold", action="store_true",
+                    help="also time boba_reorder cold (after a 512 MiB write that flushes L2 and the Infinity "
+                         "Cache); on by default for graphs of at most 2^24 edges")
     ap.add_argument("--calibrate", action="store_true",
                     help="run a plain elementwise kernel over 256 MiB (reads and writes 256 MiB) first, "
                          "to scale hardware byte counters")
@@ -275,6 +278,36 @@ def main():
     reorder_kern = boba.boba_timing_collect()
     boba.boba_timing_enable(False)
     stage_ms["reorder"] = float(np.mean([er[k][0].elapsed_time(er[k][1]) for k in range(args.steps)]))
+    cold_ms = None
+    if args.cold or m <= (1 << 24):
+        flush = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+        ct = []
+        for _ in range(args.steps):
+            flush.fill_(1)
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            e[0].record()
+            boba.boba_reorder(src, dst, n, ws=ws_r, perm=perm, order=order)
+            e[1].record()
+            torch.cuda.synchronize()
+            ct.append(e[0].elapsed_time(e[1]))
+        cold_ms = float(np.median(ct))
+        del flush
+        log(f"boba_reorder cold: {cold_ms:.3f} ms")
+    # a plain device-to-device copy of 1 GiB: the bandwidth a streaming kernel can expect here
+    cp_a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    cp_b = torch.empty_like(cp_a)
+    cp_b.copy_(cp_a)
+    cpt = []
+    for _ in range(5):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record()
+        cp_b.copy_(cp_a)
+        e[1].record()
+        torch.cuda.synchronize()
+        cpt.append(e[0].elapsed_time(e[1]))
+    copy_GBs = 2 * (1 << 30) / (float(np.median(cpt)) * 1e-3) / 1e9  # read + write
+    del cp_a, cp_b
+    log(f"device copy: {copy_GBs:.0f} GB/s")
     log(f"boba_reorder alone: {stage_ms['reorder']:.3f} ms")
 
     # the non-atomic scatter of the paper's GPU kernel (Sec. 4.4): what the
@@ -373,6 +406,7 @@ def main():
     dk = kernels[dom]
     traffic = pmc_traffic(dom, args.workload, dk["launches_per_step"])
     roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["achieved_GBs"], "peak": HBM_PEAK_GBS,
+                "frac_of_measured_copy": dk["achieved_GBs"] / copy_GBs,
                 "unit": "GB/s", "frac": dk["achieved_GBs"] / HBM_PEAK_GBS, "traffic": traffic,
                 "alg_bytes_per_launch": dk["alg_bytes_per_launch"], "avg_ms": dk["avg_ms"]}
 
@@ -415,6 +449,8 @@ def main():
         "spmv_reordered_vs_input_rel_l2": spmv_agree,
         "kernels": kernels,
         "roofline": roofline,
+        "device_copy_GBs": copy_GBs,
+        "reorder_ms_cold": cold_ms,
         "cpu_baseline": cpu,
         "batched": batched,
         "binned": binned,
