@@ -310,6 +310,26 @@ def main():
     log(f"device copy: {copy_GBs:.0f} GB/s")
     log(f"boba_reorder alone: {stage_ms['reorder']:.3f} ms")
 
+    # the standalone relabel with a given perm: one gather per endpoint vs the bucketed path
+    s_o, d_o = torch.empty_like(src), torch.empty_like(dst)
+    ws_rl = torch.empty(boba.boba_relabel_bucketed_workspace(n, m), dtype=torch.uint8, device=dev)
+    relabel_ms = {}
+    for name, fn in (("gather", lambda: boba.boba_relabel(src, dst, perm, src_out=s_o, dst_out=d_o)),
+                     ("bucketed", lambda: boba.boba_relabel_bucketed(src, dst, perm, src_out=s_o, dst_out=d_o,
+                                                                     ws=ws_rl))):
+        fn()
+        rt = []
+        for _ in range(3):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            e[0].record()
+            fn()
+            e[1].record()
+            torch.cuda.synchronize()
+            rt.append(e[0].elapsed_time(e[1]))
+        relabel_ms[name] = float(np.median(rt))
+    del s_o, d_o, ws_rl
+    log(f"standalone relabel: gather {relabel_ms['gather']:.3f} ms, bucketed {relabel_ms['bucketed']:.3f} ms")
+
     # the non-atomic scatter of the paper's GPU kernel (Sec. 4.4): what the
     # exact minimum costs here, and how much of the order the race changes
     perm_r, order_r = torch.empty_like(perm), torch.empty_like(order)
@@ -457,6 +477,7 @@ def main():
         "nbr": nbr,
         "pagerank": pagerank,
         "racy_scatter": racy,
+        "standalone_relabel_ms": relabel_ms,
         "paper_context": PAPER_CONTEXT,
         "device": torch.cuda.get_device_name(0),
         "source_digest": source_digest(),

@@ -29,6 +29,8 @@ PROTOTYPES = {
     "boba_reorder_workspace": (_SZ, [_I64, _I64]),
     "boba_reorder": (_I32, [_P, _P, _I64, _I64, _P, _P, _P, _SZ, _U32, _P]),
     "boba_relabel": (_I32, [_P, _P, _I64, _P, _I64, _P, _P, _P]),
+    "boba_relabel_bucketed_workspace": (_SZ, [_I64, _I64]),
+    "boba_relabel_bucketed": (_I32, [_P, _P, _I64, _P, _I64, _P, _P, _P, _SZ, _P]),
     "boba_reorder_relabel_workspace": (_SZ, [_I64, _I64]),
     "boba_reorder_relabel": (_I32, [_P, _P, _I64, _I64, _P, _P, _P, _P, _P, _SZ, _U32, _P]),
     "boba_bin_by_dst_workspace": (_SZ, [_I64, _I64]),
@@ -141,6 +143,26 @@ def boba_relabel(src, dst, perm, *, src_out=None, dst_out=None, stream=None):
     dst_out = torch.empty_like(dst) if dst_out is None else dst_out
     _check(load().boba_relabel(_ptr(src), _ptr(dst), src.numel(), _ptr(perm), perm.numel(), _ptr(src_out),
                                _ptr(dst_out), _stream(stream)))
+    return src_out, dst_out
+
+
+def boba_relabel_bucketed_workspace(n: int, m: int) -> int:
+    return int(load().boba_relabel_bucketed_workspace(n, m))
+
+
+def boba_relabel_bucketed(src, dst, perm, *, src_out=None, dst_out=None, ws=None, stream=None):
+    """boba_relabel through vertex buckets (no random perm reads); same results."""
+    _dev_i32(src, "src")
+    _dev_i32(dst, "dst")
+    _dev_i32(perm, "perm")
+    m, n = src.numel(), perm.numel()
+    if dst.numel() != m:
+        raise ValueError("src and dst differ in length")
+    src_out = torch.empty_like(src) if src_out is None else src_out
+    dst_out = torch.empty_like(dst) if dst_out is None else dst_out
+    ws = _workspace(boba_relabel_bucketed_workspace(n, m), src.device, ws)
+    _check(load().boba_relabel_bucketed(_ptr(src), _ptr(dst), m, _ptr(perm), n, _ptr(src_out), _ptr(dst_out),
+                                        _ptr(ws), ws.numel(), _stream(stream)))
     return src_out, dst_out
 
 

@@ -1268,3 +1268,59 @@ extern "C" boba_status boba_relabel(const int32_t *src, const int32_t *dst, int6
     if (!flag) return BOBA_ERR_HIP;
     return relabel_run(src, dst, (uint32_t)m, perm, (uint32_t)n, src_out, dst_out, flag, stream);
 }
+
+// The records, segment offsets and new IDs of the bucketed relabel (no ranking).
+struct RelabelLayout {
+    uint32_t *recs, *tile_off, *off_t, *vals;
+    size_t bytes;
+};
+
+static RelabelLayout relabel_layout(void *ws, const ReorderPlan &P) {
+    RelabelLayout L;
+    Carver c(ws);
+    L.recs = c.take<uint32_t>(P.bucketed ? (size_t)P.nt * P.region : 0);
+    L.tile_off = c.take<uint32_t>(P.bucketed ? (size_t)P.nt * (P.nb + 1) : 0);
+    L.off_t = c.take<uint32_t>(P.bucketed ? (size_t)P.nt * (P.nb + 1) : 0);
+    L.vals = c.take<uint32_t>(P.bucketed ? (size_t)P.nt * P.region : 0);
+    L.bytes = c.bytes() > 0 ? c.bytes() : 256;
+    return L;
+}
+
+extern "C" size_t boba_relabel_bucketed_workspace(int64_t n, int64_t m) {
+    if (n < 0 || m < 0 || n >= (1ll << 31) || m >= (1ll << 31)) return 0;
+    return relabel_layout(nullptr, reorder_plan(n, m)).bytes;
+}
+
+extern "C" boba_status boba_relabel_bucketed(const int32_t *src, const int32_t *dst, int64_t m, const int32_t *perm,
+                                             int64_t n, int32_t *src_out, int32_t *dst_out, void *ws,
+                                             size_t ws_bytes, hipStream_t stream) {
+    clear_error();
+    if (boba_status e = check_sizes(m, n, false)) return e;
+    if (m == 0) return BOBA_OK;
+    if (!src || !dst || !src_out || !dst_out || !perm)
+        return fail(BOBA_ERR_ARG, "boba_relabel_bucketed: NULL pointer");
+    if (n == 0) return fail(BOBA_ERR_ARG, "boba_relabel_bucketed: edges given but n = 0");
+    const size_t need = boba_relabel_bucketed_workspace(n, m);
+    if (!ws || ws_bytes < need || ((uintptr_t)ws & 255u))
+        return fail(BOBA_ERR_WORKSPACE,
+                    "boba_relabel_bucketed: workspace needs %zu bytes, 256-byte aligned (got %zu at %p)", need,
+                    ws_bytes, ws);
+    int32_t *flag = range_flag();
+    if (!flag) return BOBA_ERR_HIP;
+    const uint32_t um = (uint32_t)m, un = (uint32_t)n;
+    const ReorderPlan P = reorder_plan(n, m);
+    if (!P.bucketed || !aligned16(src) || !aligned16(dst))
+        return relabel_run(src, dst, um, perm, un, src_out, dst_out, flag, stream);
+    const RelabelLayout L = relabel_layout(ws, P);
+    BOBA_LAUNCH("bucket_split", k_bucket_split, dim3(P.nt < device_cus() ? P.nt : device_cus()), dim3(kSplitThreads),
+                stream, src, dst, um, P.tiles_half, un, P.nb, P.region, L.recs, L.tile_off, flag);
+    BOBA_LAUNCH("bucket_transpose", k_transpose, dim3(ceil_div(P.nb + 1, 32), ceil_div(P.nt, 32)), dim3(256), stream,
+                (const uint32_t *)L.tile_off, P.nt, P.nb + 1, L.off_t);
+    BOBA_LAUNCH("bucket_relabel", k_bucket_relabel, dim3(P.nb * P.slices), dim3(kMinThreads), stream,
+                (const uint32_t *)L.recs, (const uint32_t *)L.off_t, P.nt, P.region, P.nb, P.tps, min_batch(P), un,
+                perm, L.vals);
+    BOBA_LAUNCH("tile_unsplit", k_tile_unsplit, dim3(P.nt), dim3(kSplitThreads), stream, (const uint32_t *)L.recs,
+                (const uint32_t *)L.vals, (const uint32_t *)L.tile_off, P.nb, P.region, um, P.tiles_half, src_out,
+                dst_out);
+    return BOBA_OK;
+}

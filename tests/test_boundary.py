@@ -165,6 +165,18 @@ def test_pagerank_argument_errors(lib):
     assert lib.boba_pagerank(None, None, None, 0, 0, 0.85, 3, 0.0, None, None, None, None, 0, None) == boba.BOBA_OK
 
 
+def test_bucketed_relabel_argument_errors(lib):
+    need = lib.boba_relabel_bucketed_workspace(100, 1000)
+    assert need > 0 and lib.boba_relabel_bucketed_workspace(-1, 5) == 0
+    A, B, C, D = FAKE, P(0x10100), P(0x10200), P(0x10300)
+    assert lib.boba_relabel_bucketed(A, B, 1000, None, 100, C, D, A, need, None) == boba.BOBA_ERR_ARG
+    assert lib.boba_relabel_bucketed(A, B, 1000, A, 0, C, D, A, need, None) == boba.BOBA_ERR_ARG
+    assert lib.boba_relabel_bucketed(A, B, 1 << 31, A, 100, C, D, A, need, None) == boba.BOBA_ERR_OVERFLOW
+    assert lib.boba_relabel_bucketed(A, B, 1000, A, 100, C, D, A, need - 1, None) == boba.BOBA_ERR_WORKSPACE
+    assert lib.boba_relabel_bucketed(A, B, 1000, A, 100, C, D, None, need, None) == boba.BOBA_ERR_WORKSPACE
+    assert lib.boba_relabel_bucketed(None, None, 0, None, 0, None, None, None, 0, None) == boba.BOBA_OK
+
+
 def test_binding_refuses_host_tensors():
     import torch
     x = torch.zeros(4, dtype=torch.int32)

@@ -392,3 +392,30 @@ def test_racy_flag_on_the_direct_path():
     src, dst = graphgen.uniform_edges(n, m, 108)
     perm, order = boba.boba_reorder(dev(src), dev(dst), n, flags=boba.BOBA_FLAG_RACY)
     assert racy_result_is_valid(src, dst, n, host(perm), host(order))
+
+
+@pytest.mark.parametrize("n,m", [(1, 5), (5000, 7), (70001, 300007), ((1 << 20) + 3, (1 << 22) + 1)])
+def test_bucketed_relabel_matches_the_gather(n, m):
+    src, dst = graphgen.uniform_edges(n, m, 109 + n % 13)
+    perm = np.random.default_rng(110).permutation(n).astype(np.int32)
+    s_ref, d_ref = oracle.relabel(src, dst, perm)
+    s2, d2 = boba.boba_relabel_bucketed(dev(src), dev(dst), dev(perm))
+    assert np.array_equal(host(s2), s_ref) and np.array_equal(host(d2), d_ref)
+    # in place, and unaligned views (the gather path)
+    s_d, d_d = dev(src), dev(dst)
+    boba.boba_relabel_bucketed(s_d, d_d, dev(perm), src_out=s_d, dst_out=d_d)
+    assert np.array_equal(host(s_d), s_ref) and np.array_equal(host(d_d), d_ref)
+    if m > 1:
+        big_s = dev(np.concatenate([[0], src]).astype(np.int32))
+        big_d = dev(np.concatenate([[0], dst]).astype(np.int32))
+        s3, d3 = boba.boba_relabel_bucketed(big_s[1:], big_d[1:], dev(perm))
+        assert np.array_equal(host(s3), s_ref) and np.array_equal(host(d3), d_ref)
+
+
+def test_bucketed_relabel_past_2_25_vertices():
+    n, m = (1 << 25) + 7, 1 << 18
+    src, dst = graphgen.uniform_edges(n, m, 111)
+    perm = np.random.default_rng(112).permutation(n).astype(np.int32)
+    s2, d2 = boba.boba_relabel_bucketed(dev(src), dev(dst), dev(perm))
+    s_ref, d_ref = oracle.relabel(src, dst, perm)
+    assert np.array_equal(host(s2), s_ref) and np.array_equal(host(d2), d_ref)
