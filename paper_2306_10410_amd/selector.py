@@ -380,6 +380,8 @@ def main(argv=None):
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--out", default="selector_model.npz")
     ap.add_argument("--data-out", default="selector_data.npz")
+    ap.add_argument("--eval-model", default=None,
+                    help="measure the held-out graphs only and evaluate this saved model (no training)")
     args = ap.parse_args(argv)
     log = lambda s: print(f"[selector] {s}", file=sys.stderr, flush=True)
     tr_specs = selector_specs(args.train, graphgen.BASE_SEED + 50, log2_hi=args.log2_hi)
@@ -391,6 +393,19 @@ def main(argv=None):
     pool = start_pool(args.workers) if args.workers > 1 else None  # before the GPU is touched
     t0 = time.perf_counter()
     warm_up(log)
+    if args.eval_model:
+        model = load_model(args.eval_model)
+        if model is None:
+            raise SystemExit(f"{args.eval_model}: not a valid selector model")
+        Xho, _, rho = build_dataset(ho_specs, reps=args.reps, log=log, pool=pool)
+        if pool is not None:
+            pool.shutdown()
+        t_inf = time_inference(model.params)
+        res = evaluate(model.params, Xho, rho, t_inf, model.gate)
+        res.update({"model": args.eval_model, "t_infer_ms": t_inf,
+                    "t_feat_ms_median": float(np.median([r["t_feat"] for r in rho]))})
+        print(json.dumps(res), flush=True)
+        return 0
     # training and held-out graphs are measured interleaved, so that slow
     # drifts of the machine do not separate the two sets
     specs = tr_specs + ho_specs
