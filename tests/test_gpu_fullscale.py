@@ -43,6 +43,34 @@ def test_rmat24_reorder_and_relabel(rmat24):
     assert np.array_equal(s2h, s2_ref) and np.array_equal(d2h, d2_ref)
     # restricted growth of the relabelled flattened list, checked on the GPU's output
     assert restricted_growth(np.concatenate([s2h, d2h]))
+    del s2, d2, s2h, d2h
+    s3, d3 = boba.boba_relabel_bucketed(s, d, perm)  # the same relabel through vertex buckets
+    assert np.array_equal(host(s3), s2_ref) and np.array_equal(host(d3), d2_ref)
+    assert boba.boba_check_device_error() == boba.BOBA_OK
+
+
+@pytest.mark.timeout(600)
+def test_rmat24_destination_binning(rmat24):
+    g = rmat24
+    so, do = boba.boba_bin_by_dst(dev(g.src), dev(g.dst), g.n, 8)
+    so_ref, do_ref = oracle.bin_by_dst(g.src, g.dst, g.n, 8)
+    assert np.array_equal(host(so), so_ref) and np.array_equal(host(do), do_ref)
+    assert boba.boba_check_device_error() == boba.BOBA_OK
+
+
+@pytest.mark.timeout(600)
+def test_rmat20_pagerank():
+    # 20 iterations on the transposed CSR of RMAT-20 against the FP64 oracle;
+    # L1 bound 1.5 * 5e-6 * sum(0.85^k) as derived in the PageRank tests
+    g = graphgen.make_workload("rmat20")
+    rp_t, col_t, _ = oracle.coo_to_csr(g.dst, g.src, None, g.n)
+    rp_f, _, _ = oracle.coo_to_csr(g.src, g.dst, None, g.n)
+    rank, res, it = boba.boba_pagerank(dev(rp_t), dev(col_t), 0.85, 20, out_rowptr=dev(rp_f))
+    r_ref, ch_ref = oracle.pagerank(g.src, g.dst, g.n, 0.85, 20)
+    bound = 1.5 * 5e-6 * sum(0.85 ** k for k in range(20))
+    assert np.abs(host(rank).astype(np.float64) - r_ref).sum() <= bound
+    assert np.all(np.abs(host(res) - np.array(ch_ref)) <= 2 * bound)
+    assert int(host(it)[0]) == 20
     assert boba.boba_check_device_error() == boba.BOBA_OK
 
 
