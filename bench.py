@@ -130,12 +130,17 @@ def cpu_baseline(g, budget_s):
     rate = probe / max(time.perf_counter() - t, 1e-9)
     sample = int(min(g.m, max(probe, rate * budget_s)))
     s, d = np.ascontiguousarray(g.src[:sample]), np.ascontiguousarray(g.dst[:sample])
-    t = time.perf_counter()
-    oracle.boba(s, d, g.n)
-    el = time.perf_counter() - t
+    # repeated while the budget lasts (at least 3 runs, at most 10): the median run
+    runs = []
+    while len(runs) < 3 or (sum(runs) < 0.67 * budget_s and len(runs) < 10):
+        t = time.perf_counter()
+        oracle.boba(s, d, g.n)
+        runs.append(time.perf_counter() - t)
+    el = float(np.median(runs))
     what = "whole edge list" if sample == g.m else f"first {sample} of {g.m} edges (all n = {g.n} vertices)"
     return {"value": sample / el, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": f"sequential BOBA (C, -O2, 1 thread) on {what}; {el:.2f} s",
+            "sample": f"sequential BOBA (C, -O2, 1 thread) on {what}; median of {len(runs)} runs, "
+                      f"{el:.2f} s each, {sum(runs):.1f} s in all",
             "cpu_model": cpu_info()[0], "host_cpus": cpu_info()[1]}
 
 
