@@ -11,9 +11,10 @@
 //           registers, a wavefront per longer row counts the entries whose
 //           line no earlier entry of the row has (one broadcast LDS read per
 //           earlier entry).  Rows longer than kSmall are put on a list.
-//   big     a workgroup per listed row: an LDS bitmap over up to 2^20 lines,
-//           one pass per 2^20 lines of the row's [min, max] line span; an
-//           entry is new when its bit was clear.
+//   big     a workgroup per listed row with an LDS bitmap: over all lines in
+//           one pass when they number at most 2^20, else one pass per 2^20
+//           lines of the row's [min, max] line span; an entry is new when its
+//           bit was clear.
 //   reduce  the per-row ratios summed in a fixed order (per part of the rows,
 //           then over the parts), so the result is bit-reproducible.
 #include <algorithm>
