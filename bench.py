@@ -48,13 +48,21 @@ PAPER_CONTEXT = {
 }
 
 
+def radix_passes(n):
+    """8-bit LSD passes coo_to_csr makes over row IDs below n."""
+    bits = max(0, (n - 1).bit_length()) if n > 1 else 0
+    return max(1, (bits + 7) // 8)
+
+
 def kernel_alg_bytes(name, n, m):
     """Algorithmic bytes per launch: what the kernel must read and write at
     minimum given its inputs and outputs (int32 / float32 = 4 bytes)."""
     table = {
         "scatter_min": 8 * m + 4 * n,          # read src, dst; write r once
         "relabel": 16 * m + 4 * n,             # read src, dst, perm once; write both
-        "radix_scatter": 24 * m,               # read key, col, val; write them
+        # read key, col, val; write them (the last pass writes no keys):
+        # the mean over the ceil(bits(n - 1) / 8) passes
+        "radix_scatter": (24 * m * (radix_passes(n) - 1) + 20 * m) // radix_passes(n),
         "spmv": 8 * m + 4 * (n + 1) + 8 * n,   # val, col, rowptr, x once, y
         "bucket_split": 16 * m,                # read src, dst; write one record each
         "bucket_min": 8 * m + 4 * n,           # read the records; write r

@@ -83,7 +83,13 @@ __global__ __launch_bounds__(kHistThreads) void k_radix_hist(const int32_t *__re
 }
 
 // amdgpu_waves_per_eu(8): at most 64 VGPRs, so that two workgroups share a CU
-template <int BITS, bool HAS_VAL>
+// LAST (the final pass of coo_to_csr): the sorted keys themselves are not
+// needed, only where rows end.  Inside a tile's digit run consecutive slots
+// are consecutive output positions, so a key change there is a row end and
+// rowptr[key + 1] is written directly; only the first and last key of every
+// run are stored (into keys_out at their positions), for k_run_ends to
+// settle the row ends that fall on run boundaries.
+template <int BITS, bool HAS_VAL, bool LAST = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_radix_scatter(const int32_t *__restrict__ keys_in,
                                                           const int32_t *__restrict__ col_in,
                                                           const float *__restrict__ val_in, uint32_t m,
@@ -91,7 +97,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
                                                           const uint32_t *__restrict__ offs,
                                                           int32_t *__restrict__ keys_out,
                                                           int32_t *__restrict__ col_out,
-                                                          float *__restrict__ val_out) {
+                                                          float *__restrict__ val_out,
+                                                          uint32_t n_rows = 0, uint32_t *__restrict__ rowptr = nullptr,
+                                                          int32_t *flag = nullptr) {
     constexpr uint32_t BINS = 1u << BITS;
     constexpr uint32_t MASK = BINS - 1;
     // digits per thread in the tile scan (threads beyond BINS hold none)
@@ -196,11 +204,31 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
         const uint32_t g = s_gofs[s_dig[p]] + p;
         return g < m ? g : m;
     };
+    if (LAST) {
+        bool bad = false;
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-        const uint32_t p = j * kBlock + threadIdx.x;
-        const uint32_t g = dest(p);
-        if (g < m) keys_out[g] = s_buf[p];
+        for (int j = 0; j < kItems; ++j) {
+            const uint32_t p = j * kBlock + threadIdx.x;
+            const uint32_t g = dest(p);
+            if (g >= m) continue;
+            const int32_t key = s_buf[p];
+            const uint8_t dg = s_dig[p];
+            const bool run_end = p + 1 == count || s_dig[p + 1] != dg;
+            if (p == 0 || s_dig[p - 1] != dg || run_end) keys_out[g] = key;
+            if ((uint32_t)key >= n_rows) {
+                bad = true;
+                continue;
+            }
+            if (!run_end && s_buf[p + 1] != key) rowptr[key + 1] = g + 1;
+        }
+        if (bad) flag_range_error(flag);
+    } else {
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const uint32_t p = j * kBlock + threadIdx.x;
+            const uint32_t g = dest(p);
+            if (g < m) keys_out[g] = s_buf[p];
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -283,42 +311,27 @@ __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *__restrict__ a, u
     for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) a[i] = v;
 }
 
-// rowptr[row + 1] <- end of row's run in the sorted keys.  Four keys per
-// thread (one int4 load when the keys are 16-byte aligned) plus the next key.
-__device__ __forceinline__ void row_end(int32_t key, int32_t next, uint32_t k, uint32_t m, uint32_t n_rows,
-                                        uint32_t *__restrict__ rowptr, bool &bad) {
-    if ((uint32_t)key >= n_rows) {
-        bad = true;
-        return;
+// The row ends on digit-run boundaries of the last pass: run (t, d) of the
+// output (runs lie digit-major, then by tile) ends just before the next run
+// starts; if its last key differs from the next run's first key (or it is the
+// last run), that key's row ends there.  The first and last key of every run
+// were stored by the last pass.  offs holds each run's global start.
+template <int BITS>
+__global__ __launch_bounds__(256) void k_run_ends(const uint32_t *__restrict__ offs, uint32_t tiles,
+                                                  const int32_t *__restrict__ keys, uint32_t m, uint32_t n_rows,
+                                                  uint32_t *__restrict__ rowptr) {
+    constexpr uint32_t BINS = 1u << BITS;
+    const uint64_t runs = (uint64_t)tiles * BINS;
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t q = (uint64_t)blockIdx.x * 256 + threadIdx.x; q < runs; q += stride) {
+        const uint32_t t = (uint32_t)(q / BINS), d = (uint32_t)(q % BINS);
+        const uint32_t start = offs[q];
+        const uint32_t next = t + 1 < tiles ? offs[q + BINS] : (d + 1 < BINS ? offs[d + 1] : m);
+        if (next <= start || next > m) continue;  // empty run
+        const int32_t key = keys[next - 1];
+        if ((uint32_t)key >= n_rows) continue;    // flagged by the scatter
+        if (next == m || keys[next] != key) rowptr[key + 1] = next;
     }
-    if (k + 1 == m || next != key) rowptr[key + 1] = k + 1;
-}
-
-__global__ __launch_bounds__(kBlock) void k_row_ends(const int32_t *__restrict__ keys, uint32_t m, uint32_t n_rows,
-                                                     uint32_t *__restrict__ rowptr, int32_t *flag) {
-    const uint32_t stride = gridDim.x * kBlock;
-    const uint32_t groups = (m + 3) / 4;
-    const bool vec = (((uintptr_t)keys) & 15u) == 0;
-    bool bad = false;
-    for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < groups; q += stride) {
-        const uint32_t k = 4 * q;
-        int32_t v[5];
-        if (vec && k + 3 < m) {
-            const v4i x = *(const v4i *)(keys + k);
-            v[0] = x.x;
-            v[1] = x.y;
-            v[2] = x.z;
-            v[3] = x.w;
-        } else {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) v[j] = k + j < m ? keys[k + j] : 0;
-        }
-        v[4] = k + 4 < m ? keys[k + 4] : 0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (k + j < m) row_end(v[j], v[j + 1], k + j, m, n_rows, rowptr, bad);
-    }
-    if (bad) flag_range_error(flag);
 }
 
 constexpr int kBits = 8;
@@ -393,6 +406,7 @@ extern "C" boba_status coo_to_csr(const int32_t *row, const int32_t *col, const 
     const float *vin = val;
     for (int p = 0; p < passes; ++p) {
         const uint32_t shift = (uint32_t)(p * kBits);
+        const bool last = p + 1 == passes;
         const bool to_out = ((passes - 1 - p) % 2) == 0;
         int32_t *kout = (p % 2 == 0) ? L.keys_a : L.keys_b;
         int32_t *cout = to_out ? col_out : L.col_x;
@@ -406,18 +420,25 @@ extern "C" boba_status coo_to_csr(const int32_t *row, const int32_t *col, const 
             return e;
         BOBA_LAUNCH("radix_offsets", k_col_down<1 << kBits>, dim3(L.colblocks), dim3(1 << kBits), stream, L.hist,
                     L.tiles, L.colblocks, (const uint32_t *)L.colpart);
-        if (has_val)
+        const uint32_t *offs = L.hist;
+        if (has_val && last)
+            BOBA_LAUNCH("radix_scatter", (k_radix_scatter<kBits, true, true>), dim3(L.tiles), dim3(kBlock), stream,
+                        kin, cin, vin, um, shift, L.tiles, offs, kout, cout, vout, nr, (uint32_t *)rowptr, flag);
+        else if (last)
+            BOBA_LAUNCH("radix_scatter", (k_radix_scatter<kBits, false, true>), dim3(L.tiles), dim3(kBlock), stream,
+                        kin, cin, vin, um, shift, L.tiles, offs, kout, cout, vout, nr, (uint32_t *)rowptr, flag);
+        else if (has_val)
             BOBA_LAUNCH("radix_scatter", (k_radix_scatter<kBits, true>), dim3(L.tiles), dim3(kBlock), stream, kin, cin,
-                        vin, um, shift, L.tiles, (const uint32_t *)L.hist, kout, cout, vout);
+                        vin, um, shift, L.tiles, offs, kout, cout, vout);
         else
             BOBA_LAUNCH("radix_scatter", (k_radix_scatter<kBits, false>), dim3(L.tiles), dim3(kBlock), stream, kin, cin,
-                        vin, um, shift, L.tiles, (const uint32_t *)L.hist, kout, cout, vout);
+                        vin, um, shift, L.tiles, offs, kout, cout, vout);
         kin = kout;
         cin = cout;
         vin = vout;
     }
-    BOBA_LAUNCH("row_ends", k_row_ends, dim3(grid_for((um + 3) / 4, kBlock)), dim3(kBlock), stream, kin, um, nr,
-                (uint32_t *)rowptr, flag);
+    BOBA_LAUNCH("row_ends", k_run_ends<kBits>, dim3(grid_for((uint64_t)L.tiles << kBits, 256)), dim3(256), stream,
+                (const uint32_t *)L.hist, L.tiles, kin, um, nr, (uint32_t *)rowptr);
     return device_scan<OpMax, true>("rowptr_scan", LoadArr{(const uint32_t *)rowptr}, StoreArr{(uint32_t *)rowptr}, nr + 1,
                                     L.partial, stream);
 }

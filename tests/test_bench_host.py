@@ -23,7 +23,9 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 def test_algorithmic_bytes_table():
     n, m = 1 << 24, 1 << 28
     assert bench.kernel_alg_bytes("bucket_split", n, m) == 16 * m
-    assert bench.kernel_alg_bytes("radix_scatter", n, m) == 24 * m
+    # three 8-bit passes for 24-bit row IDs; the last one writes no keys
+    assert bench.radix_passes(n) == 3 and bench.radix_passes(256) == 1 and bench.radix_passes(257) == 2
+    assert bench.kernel_alg_bytes("radix_scatter", n, m) == (2 * 24 * m + 20 * m) // 3
     assert bench.kernel_alg_bytes("spmv", n, m) == 8 * m + 4 * (n + 1) + 8 * n
     assert bench.kernel_alg_bytes("no_such_kernel", n, m) is None
 
