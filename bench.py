@@ -105,25 +105,40 @@ KERNEL_FN = {"bucket_transpose": "k_transpose", "csr_fill": "k_fill_u32", "relab
              "scatter_min": "k_scatter_min_vec", "spmv": "k_spmv_chunk", "mark": "k_mark_merge"}
 
 
+# the instantiations a kernel's step launches take, where a summary holds
+# several (coo_to_csr in the step carries values; its last pass writes no keys)
+PMC_VARIANT = {"radix_scatter": "<8,true,", "spmv": "<true>"}
+
+
 def pmc_traffic(kernel, workload, launches_per_step):
     """HBM bytes per launch from a committed rocprofv3 PMC summary, if it was
-    taken on the current kernel sources; otherwise None."""
+    taken on the current kernel sources; otherwise None.  A summary may hold
+    several template instantiations: the step's ones are averaged, weighted
+    by their dispatches."""
     fn = KERNEL_FN.get(kernel, "k_" + kernel)
     path = os.path.join(ROOT, "profiles", f"pmc_{fn}_{workload}.txt")
     if not os.path.exists(path):
         return None
-    vals = {}
+    sections, cur = [], None
     with open(path) as f:
         for line in f:
-            if ":" in line and not line.startswith("#"):
+            if line.startswith("# rocprofv3 PMC HBM traffic of "):
+                cur = {"name": line[len("# rocprofv3 PMC HBM traffic of "):].split(", workload")[0]}
+                sections.append(cur)
+            elif cur is not None and ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
-                vals[k.strip()] = v.strip()
-    if vals.get("source_digest") != source_digest():
-        return None
+                cur[k.strip()] = v.strip()
+    want = PMC_VARIANT.get(kernel)
+    if want is not None:
+        sections = [x for x in sections if want in x["name"]]
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        if not sections or any(x.get("source_digest") != source_digest() for x in sections):
+            return None
+        n = [int(x["dispatches"]) for x in sections]
+        b = [float(x["hbm_bytes_per_launch"]) for x in sections]
     except (KeyError, ValueError):
         return None
+    return sum(ni * bi for ni, bi in zip(n, b)) / sum(n)
 
 
 def cpu_baseline(g, budget_s):

@@ -35,10 +35,24 @@ def test_pmc_traffic_requires_a_matching_source_digest(tmp_path, monkeypatch):
     prof.mkdir()
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "source_digest", lambda: "abc123")
-    (prof / "pmc_k_radix_scatter_w.txt").write_text("# x\nsource_digest: abc123\nhbm_bytes_per_launch: 42\n")
-    assert bench.pmc_traffic("radix_scatter", "w", 3) == 42.0
-    (prof / "pmc_k_radix_scatter_w.txt").write_text("source_digest: stale\nhbm_bytes_per_launch: 42\n")
-    assert bench.pmc_traffic("radix_scatter", "w", 3) is None
+
+    def section(name, digest, dispatches, hbm):
+        return (f"# rocprofv3 PMC HBM traffic of {name}, workload w\nsource_digest: {digest}\n"
+                f"dispatches: {dispatches}\nhbm_bytes_per_launch: {hbm}\n")
+
+    f = prof / "pmc_k_radix_scatter_w.txt"
+    # the step's instantiations, weighted by dispatches; the others ignored
+    f.write_text(section("k_radix_scatter<8,false,false>", "abc123", 8, 1000) +
+                 section("k_radix_scatter<8,true,false>", "abc123", 12, 60) +
+                 section("k_radix_scatter<8,true,true>", "abc123", 6, 30))
+    assert bench.pmc_traffic("radix_scatter", "w", 3) == 50.0
+    f.write_text(section("k_radix_scatter<8,true,false>", "stale", 12, 60) +
+                 section("k_radix_scatter<8,true,true>", "abc123", 6, 30))
+    assert bench.pmc_traffic("radix_scatter", "w", 3) is None   # a kernel changed since
+    f.write_text(section("k_radix_scatter<8,false,false>", "abc123", 8, 1000))
+    assert bench.pmc_traffic("radix_scatter", "w", 3) is None   # not the step's instantiation
+    (prof / "pmc_k_bucket_split_w.txt").write_text(section("k_bucket_split", "abc123", 9, 42))
+    assert bench.pmc_traffic("bucket_split", "w", 1) == 42.0
     assert bench.pmc_traffic("spmv", "w", 1) is None  # no summary
 
 
