@@ -1,7 +1,9 @@
 /*
  * boba.h -- C ABI of libboba.so, an MI355X (gfx950) implementation of the
  * data-parallel hot path of BOBA (Batched Order By Attachment, arXiv
- * 2306.10410): first-occurrence reorder -> edge relabel -> COO->CSR -> SpMV.
+ * 2306.10410): first-occurrence reorder -> edge relabel -> COO->CSR -> SpMV,
+ * with batched plans, a learned reorder selector, destination binning, the
+ * NBR locality metric and PageRank.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -18,7 +20,7 @@
  *    out-of-range ID is skipped and recorded in a per-device flag; read and
  *    clear it with boba_check_device_error.  Results are unspecified then.
  *  - Results are deterministic: bit-identical across runs, launch shapes and
- *    tuning choices.
+ *    tuning choices (BOBA_FLAG_RACY excepted, by design).
  *  - boba_last_error() returns a thread-local description of the last failure.
  */
 #ifndef BOBA_H
