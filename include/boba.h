@@ -228,8 +228,9 @@ BOBA_API boba_status boba_bin_by_dst(const int32_t *src, const int32_t *dst, int
  *   out_rowptr   int32[n+1] row pointer of the forward CSR (row u lists the
  *                edges leaving u), giving the out-degrees in one coalesced
  *                pass; or NULL: they are then counted from col with one
- *                atomic per edge (much slower on large graphs: 12 ms for
- *                2^28 edges on 2^24 vertices).  Must describe the same graph.
+ *                atomic per distinct vertex of every 8192 edges (much
+ *                slower on large graphs: 10 ms for 2^28 edges on 2^24
+ *                vertices).  Must describe the same graph.
  *   damping      in [0, 1] (0.85 is the usual choice).
  *   max_iter     iterations to run (>= 0).
  *   tol          > 0: stop after the first iteration k whose L1 change

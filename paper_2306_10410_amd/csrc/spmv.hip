@@ -210,15 +210,51 @@ __global__ __launch_bounds__(kThreads) void k_pr_outdeg_rowptr(const int32_t *__
     }
 }
 
-// Out-degrees counted from the transposed graph's columns (one atomic per edge).
+// Out-degrees counted from the transposed graph's columns.  A workgroup takes
+// kOutChunk entries at a time and first counts them in an LDS hash table
+// (up to kProbe slots tried; an entry that finds none is counted in global
+// memory directly), then adds one global atomic per distinct vertex: the
+// hubs of a power-law graph, which occur many times in every chunk, no longer
+// queue on one counter.  Counts are integers, so the order does not matter.
+constexpr uint32_t kOutHash = 4096;
+constexpr uint32_t kOutChunk = 8192;
+constexpr uint32_t kProbe = 8;
+constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
+
 __global__ __launch_bounds__(kThreads) void k_pr_outdeg(const int32_t *__restrict__ col, uint32_t nnz, uint32_t n,
                                                         uint32_t *__restrict__ outdeg, int32_t *flag) {
-    const uint32_t stride = gridDim.x * kThreads;
+    __shared__ uint32_t keys[kOutHash];
+    __shared__ uint32_t cnts[kOutHash];
     bool bad = false;
-    for (uint32_t e = blockIdx.x * kThreads + threadIdx.x; e < nnz; e += stride) {
-        const uint32_t u = (uint32_t)col[e];
-        if (u < n) atomicAdd(&outdeg[u], 1u);
-        else bad = true;
+    for (uint64_t c0 = (uint64_t)blockIdx.x * kOutChunk; c0 < nnz; c0 += (uint64_t)gridDim.x * kOutChunk) {
+        for (uint32_t i = threadIdx.x; i < kOutHash; i += kThreads) {
+            keys[i] = kEmptyKey;
+            cnts[i] = 0;
+        }
+        __syncthreads();
+        const uint32_t c1 = (uint32_t)min<uint64_t>(nnz, c0 + kOutChunk);
+        for (uint32_t e = (uint32_t)c0 + threadIdx.x; e < c1; e += kThreads) {
+            const uint32_t u = (uint32_t)col[e];
+            if (u >= n) {
+                bad = true;
+                continue;
+            }
+            uint32_t h = (u * 2654435761u) >> 20;  // 12 bits: a slot of the 4096
+            bool done = false;
+            for (uint32_t t = 0; t < kProbe && !done; ++t) {
+                const uint32_t old = atomicCAS(&keys[h], kEmptyKey, u);
+                if (old == kEmptyKey || old == u) {
+                    atomicAdd(&cnts[h], 1u);
+                    done = true;
+                }
+                h = (h + 1) & (kOutHash - 1);
+            }
+            if (!done) atomicAdd(&outdeg[u], 1u);
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < kOutHash; i += kThreads)
+            if (keys[i] != kEmptyKey) atomicAdd(&outdeg[keys[i]], cnts[i]);
+        __syncthreads();
     }
     if (bad) flag_range_error(flag);
 }
@@ -433,8 +469,8 @@ extern "C" boba_status boba_pagerank(const int32_t *rowptr, const int32_t *col, 
             BOBA_LAUNCH("pr_outdeg", k_pr_outdeg_rowptr, dim3(grid_for(un, kThreads * 4)), dim3(kThreads), stream,
                         out_rowptr, un, ue, L.outdeg);
         else
-            BOBA_LAUNCH("pr_outdeg", k_pr_outdeg, dim3(grid_for(ue, kThreads * 4)), dim3(kThreads), stream, col, ue,
-                        un, L.outdeg, flag);
+            BOBA_LAUNCH("pr_outdeg", k_pr_outdeg, dim3(grid_for(ue, kOutChunk, 2048)), dim3(kThreads), stream, col,
+                        ue, un, L.outdeg, flag);
         BOBA_LAUNCH("spmv_split", k_spmv_split, dim3(ceil_div(S.nchunk + 1ull, kThreads)), dim3(kThreads), stream,
                     rowptr, un, (int32_t)ue, S.nchunk, S.split_i, S.split_j);
     }
