@@ -75,6 +75,31 @@ def test_rmat20_pagerank():
 
 
 @pytest.mark.timeout(600)
+def test_rmat24_pagerank_properties(rmat24):
+    # properties that hold at any size (the FP64 oracle is compared at RMAT-20):
+    # ranks sum to 1; reordering permutes them; the L1 change of each
+    # iteration shrinks by the damping factor (the iteration is a contraction)
+    g = rmat24
+    a, iters = 0.85, 20
+    bound = 1.5 * 5e-6 * sum(a ** k for k in range(iters))
+    perm, _, s2, d2 = boba.boba_reorder_relabel(dev(g.src), dev(g.dst), g.n)
+    ranks = []
+    for src_d, dst_d in ((dev(g.src), dev(g.dst)), (s2, d2)):
+        rp_t, col_t, _ = boba.coo_to_csr(dst_d, src_d, None, g.n)  # row v: sources of the edges into v
+        rp_f, _, _ = boba.coo_to_csr(src_d, dst_d, None, g.n)
+        rank, res, _ = boba.boba_pagerank(rp_t, col_t, a, iters, out_rowptr=rp_f)
+        r = host(rank).astype(np.float64)
+        assert abs(r.sum() - 1.0) <= bound and np.all(r > 0)
+        res_h = host(res)
+        assert np.all(res_h[1:] <= a * res_h[:-1] * (1 + 1e-3) + 1e-7)
+        ranks.append(r)
+        del rp_t, col_t, rp_f, rank, res
+    p = host(perm)
+    assert np.abs(ranks[1][p] - ranks[0]).sum() <= 2 * bound
+    assert boba.boba_check_device_error() == boba.BOBA_OK
+
+
+@pytest.mark.timeout(600)
 def test_rmat24_csr_and_spmv(rmat24):
     g = rmat24
     p_ref, _ = oracle.boba(g.src, g.dst, g.n)
