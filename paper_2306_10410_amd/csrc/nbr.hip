@@ -7,10 +7,12 @@
 //           being a row or an entry (row r starts at item r + rowptr[r]), so
 //           runs of empty rows are shared out like entries
 //   chunk   a workgroup per chunk stages the line IDs of its rows' entries in
-//           LDS; a lane per row of up to kTiny entries compares them in
-//           registers, a wavefront per longer row counts the entries whose
-//           line no earlier entry of the row has (one broadcast LDS read per
-//           earlier entry).  Rows longer than kSmall are put on a list.
+//           LDS and finds each entry's row by a max-scan of the rows' first
+//           entries; a lane per entry then inserts (row, line) into an LDS
+//           hash set (the insertion that finds the pair absent is a new
+//           line), and the first lane of each row's run in a wavefront adds
+//           the run's new lines to the row's count.  Rows longer than kSmall
+//           are put on a list.
 //   big     a workgroup per listed row with an LDS bitmap: over all lines in
 //           one pass when they number at most 2^20, else one pass per 2^20
 //           lines of the row's [min, max] line span; an entry is new when its
@@ -26,9 +28,17 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr uint32_t kChunkE = 2048;                // items (rows + entries) per chunk
-constexpr uint32_t kTiny = 8;                     // longest row a single lane counts
 constexpr uint32_t kSmall = 256;                  // longest row a wavefront counts
 constexpr uint32_t kWin = kChunkE + kSmall;       // entries a chunk stages
+constexpr uint32_t kPerThread = kWin / kThreads;  // staged entries per thread in the row scan
+constexpr uint32_t kRowsPerThread = kChunkE / kThreads;  // rows of a chunk per thread
+constexpr uint32_t kNotCounted = 0xFFFFFFFFu;     // count slot of rows the chunk does not count
+constexpr uint32_t kTableBits = 12;               // hash set of a chunk's (row, line) pairs
+constexpr uint32_t kTable = 1u << kTableBits;
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+static_assert(kWin % kThreads == 0 && kChunkE % kThreads == 0 && kThreads % kWave == 0,
+              "the window and the rows split evenly over the threads");
+static_assert(kTable > kWin, "a free slot is always left");
 constexpr int kBigThreads = 1024;
 constexpr uint32_t kBitmapWords = 32768;          // 128 KB: 2^20 lines per pass
 constexpr uint32_t kParts = 1024;                 // parts of the rows in the reduction
@@ -37,11 +47,10 @@ __device__ __forceinline__ uint32_t clamp_ptr(int32_t p, uint32_t nnz) {
     return p < 0 ? 0u : min((uint32_t)p, nnz);
 }
 
-// chunk_row[c] = first row r with r + rowptr[r] >= c * kChunkE (n_rows for
-// c = nchunk); also clears the big-row counter.
+// chunk[c] = {r, rowptr[r]} for the first row r with r + rowptr[r] >=
+// c * kChunkE (r = n_rows for c = nchunk); also clears the big-row counter.
 __global__ __launch_bounds__(kThreads) void k_nbr_split(const int32_t *__restrict__ rowptr, uint32_t n_rows,
-                                                        uint32_t nnz, uint32_t nchunk,
-                                                        uint32_t *__restrict__ chunk_row,
+                                                        uint32_t nnz, uint32_t nchunk, uint2 *__restrict__ chunk,
                                                         uint32_t *__restrict__ big_count) {
     const uint32_t c = blockIdx.x * kThreads + threadIdx.x;
     if (c == 0) *big_count = 0;
@@ -57,86 +66,144 @@ __global__ __launch_bounds__(kThreads) void k_nbr_split(const int32_t *__restric
             else hi = mid;
         }
     }
-    chunk_row[c] = lo;
+    chunk[c] = make_uint2(lo, clamp_ptr(rowptr[lo], nnz));
 }
 
 __global__ __launch_bounds__(kThreads) void k_nbr_chunk(const int32_t *__restrict__ rowptr,
                                                         const int32_t *__restrict__ col, uint32_t n_cols,
                                                         uint32_t nnz, uint32_t shift,
-                                                        const uint32_t *__restrict__ chunk_row,
+                                                        const uint2 *__restrict__ chunk,
                                                         uint32_t *__restrict__ nd_out,
                                                         uint32_t *__restrict__ big_list, uint32_t max_big,
                                                         uint32_t *__restrict__ big_count, int32_t *flag) {
     __shared__ uint32_t lines[kWin];
-    const uint32_t c = blockIdx.x;
-    const uint32_t r_lo = chunk_row[c], r_hi = chunk_row[c + 1];
+    __shared__ uint16_t rowof[kWin];      // 1 + the chunk-local row of each staged entry (0: none)
+    __shared__ uint32_t rcnt[kChunkE];    // distinct lines of each counted row; kNotCounted for the others
+    __shared__ uint32_t table[kTable];    // hash set of (row, line): the staged entry that holds the pair
+    __shared__ uint32_t red[kThreads / kWave];
+    const uint2 first = chunk[blockIdx.x], next = chunk[blockIdx.x + 1];
+    const uint32_t r_lo = first.x, r_hi = next.x;
     if (r_lo >= r_hi) return;
     // the chunk's rows start within kChunkE entries of the first one, so
     // every row that is not listed ends by base + kChunkE + kSmall
-    const uint32_t base = clamp_ptr(rowptr[r_lo], nnz);
-    const uint32_t wend = min(clamp_ptr(rowptr[r_hi], nnz), min(nnz, base + kChunkE + kSmall));
+    const uint32_t base = first.y;
+    const uint32_t wend = min(next.y, min(nnz, base + kChunkE + kSmall));
     const uint32_t cnt = wend > base ? min(wend - base, kWin) : 0u;
-    for (uint32_t i = threadIdx.x; i < cnt; i += kThreads) {
-        const uint32_t v = (uint32_t)col[base + i];
-        if (v >= n_cols) flag_range_error(flag);
-        lines[i] = v >> shift;
+    // a chunk holds at most kChunkE rows (r + rowptr[r] grows with r); more
+    // can only come from a malformed rowptr and are given 0 below
+    const uint32_t nrows = r_hi - r_lo;
+    // every load of the window and of the rows' bounds in flight at once
+    uint32_t v[kPerThread], s[kRowsPerThread], e[kRowsPerThread];
+#pragma unroll
+    for (uint32_t k = 0; k < kPerThread; ++k) {
+        const uint32_t i = threadIdx.x + k * kThreads;
+        v[k] = i < cnt ? (uint32_t)col[base + i] : 0u;
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kRowsPerThread; ++k) {
+        const uint32_t j = threadIdx.x + k * kThreads;
+        s[k] = j < nrows ? clamp_ptr(rowptr[r_lo + j], nnz) : 0u;
+        e[k] = j < nrows ? clamp_ptr(rowptr[r_lo + j + 1], nnz) : 0u;
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kPerThread; ++k) {
+        const uint32_t i = threadIdx.x + k * kThreads;
+        if (i < cnt) {
+            if (v[k] >= n_cols) flag_range_error(flag);
+            lines[i] = v[k] >> shift;
+        }
+        rowof[i] = 0;
+    }
+    for (uint32_t h = threadIdx.x; h < kTable; h += kThreads) table[h] = kEmpty;
+    __syncthreads();
+    // rows longer than kSmall go on the list (stored at the end, so that the
+    // counter's reply is not waited for here), empty ones get 0, the others
+    // mark their first entry
+    uint32_t slot[kRowsPerThread];
+#pragma unroll
+    for (uint32_t k = 0; k < kRowsPerThread; ++k) {
+        const uint32_t j = threadIdx.x + k * kThreads;
+        const bool ok = j < nrows;
+        const uint32_t d = e[k] > s[k] ? e[k] - s[k] : 0u;
+        const bool big = ok && d > kSmall;
+        slot[k] = big ? atomicAdd(big_count, 1u) : ~0u;
+        const bool staged = ok && d > 0 && s[k] >= base && s[k] - base < cnt;
+        const bool counted = staged && !big && s[k] - base + d <= cnt;
+        if (staged) rowof[s[k] - base] = (uint16_t)(j + 1);  // listed rows too: their entries are skipped
+        if (ok) rcnt[j] = counted ? 0u : kNotCounted;
+        if (ok && !big && !counted) nd_out[r_lo + j] = 0;
+    }
+    for (uint32_t j = kChunkE + threadIdx.x; j < nrows; j += kThreads) {
+        const uint32_t r = r_lo + j;
+        const uint32_t rs = clamp_ptr(rowptr[r], nnz), re = clamp_ptr(rowptr[r + 1], nnz);
+        if (re > rs && re - rs > kSmall) {
+            const uint32_t i = atomicAdd(big_count, 1u);
+            if (i < max_big) big_list[i] = r;
+        } else {
+            nd_out[r] = 0;
+        }
     }
     __syncthreads();
+    // the row of entry i is the last row marked at or before i (max-scan)
+    {
+        uint32_t loc[kPerThread], m = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kPerThread; ++k) {
+            loc[k] = rowof[threadIdx.x * kPerThread + k];
+            m = max(m, loc[k]);
+        }
+        uint32_t total;
+        uint32_t run = block_exclusive_scan<kThreads>(m, OpMax{}, red, total);
+#pragma unroll
+        for (uint32_t k = 0; k < kPerThread; ++k) {
+            run = max(run, loc[k]);
+            rowof[threadIdx.x * kPerThread + k] = (uint16_t)run;
+        }
+    }
+    __syncthreads();
+    // a lane per entry inserts (row, line) into the hash set; the entry whose
+    // insertion finds the pair absent is the row's first in that line
     const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t wave = threadIdx.x / kWave;
-    constexpr uint32_t NW = kThreads / kWave;
-    for (uint32_t rb = r_lo + wave * kWave; rb < r_hi; rb += NW * kWave) {
-        const uint32_t r = rb + lane;
-        const bool valid = r < r_hi;
-        const uint32_t s = valid ? clamp_ptr(rowptr[r], nnz) : 0u;
-        const uint32_t e = valid ? clamp_ptr(rowptr[r + 1], nnz) : 0u;
-        const uint32_t d = e > s ? e - s : 0u;
-        const bool big = valid && d > kSmall;
-        if (big) {
-            const uint32_t i = atomicAdd(big_count, 1u);
-            if (i < max_big) big_list[i] = r;  // always, unless rowptr is malformed
-        }
-        // rows outside the staged window can only come from a malformed rowptr
-        const bool small = valid && d > 0 && !big && s >= base && s - base + d <= cnt;
-        uint32_t mine = 0;
-        if (small && d <= kTiny) {
-            uint32_t x[kTiny];
-#pragma unroll
-            for (uint32_t q = 0; q < kTiny; ++q) x[q] = q < d ? lines[s - base + q] : 0u;
-#pragma unroll
-            for (uint32_t q = 0; q < kTiny; ++q) {
-                bool seen = q >= d;
-#pragma unroll
-                for (uint32_t t = 0; t < q; ++t) seen |= x[t] == x[q];
-                mine += !seen;
+    for (uint32_t i0 = (threadIdx.x / kWave) * kWave; i0 < cnt; i0 += kThreads) {
+        const uint32_t i = i0 + lane;  // < kWin: cnt <= kWin, a multiple of kWave
+        const bool in = i < cnt;
+        const uint32_t j1 = in ? rowof[i] : 0u;
+        const bool act = j1 != 0 && rcnt[j1 - 1] != kNotCounted;
+        bool is_new = false;
+        if (act) {
+            const uint32_t my = lines[i];
+            // linear probing ends: the table has more slots than a chunk has entries
+            uint32_t h = ((my * 0x9E3779B1u) ^ (j1 * 0x85EBCA77u)) >> (32 - kTableBits);
+            for (;;) {
+                const uint32_t old = atomicCAS(&table[h], kEmpty, i);
+                if (old == kEmpty) {
+                    is_new = true;
+                    break;
+                }
+                if (lines[old] == my && rowof[old] == j1) break;  // old < cnt: a staged entry
+                h = (h + 1) & (kTable - 1);
             }
         }
-        for (uint64_t mk = __ballot(small && d > kTiny); mk; mk &= mk - 1) {
-            const uint32_t j = (uint32_t)__builtin_ctzll(mk);
-            const uint32_t sj = __shfl(s - base, j, kWave), dj = __shfl(d, j, kWave);
-            const uint32_t nk = (dj + kWave - 1) / kWave;
-            uint32_t my[kSmall / kWave];
-            bool dup[kSmall / kWave];
-#pragma unroll
-            for (uint32_t k = 0; k < kSmall / kWave; ++k) {
-                const uint32_t q = lane + k * kWave;
-                my[k] = q < dj ? lines[sj + q] : 0u;
-                dup[k] = false;
-            }
-            // entry q repeats a line when an earlier entry t < q has it
-            for (uint32_t t = 0; t + 1 < dj; ++t) {
-                const uint32_t x = lines[sj + t];
-#pragma unroll
-                for (uint32_t k = 0; k < kSmall / kWave; ++k)
-                    if (k < nk) dup[k] |= (lane + k * kWave > t) && x == my[k];
-            }
-            uint32_t nd = 0;
-#pragma unroll
-            for (uint32_t k = 0; k < kSmall / kWave; ++k)
-                if (k < nk) nd += (uint32_t)__popcll(__ballot(lane + k * kWave < dj && !dup[k]));
-            if (lane == j) mine = nd;
+        // the lanes of one row are consecutive: the first lane of each run
+        // adds the run's new lines to the row's count
+        const uint64_t fresh = __ballot(is_new);
+        const uint32_t jp = in && lane > 0 ? rowof[i - 1] : 0u;
+        const bool head = in && (lane == 0 || jp != j1);
+        const uint64_t heads = __ballot(head);
+        if (act && head) {
+            const uint64_t above = lane + 1 < kWave ? (heads >> (lane + 1)) << (lane + 1) : 0ull;
+            const uint64_t end = above & (~above + 1);  // lowest head above this lane, 0 if none
+            const uint64_t run = (end ? end - 1 : ~0ull) & (~0ull << lane);
+            const uint32_t n = (uint32_t)__popcll(fresh & run);
+            if (n) atomicAdd(&rcnt[j1 - 1], n);
         }
-        if (valid && !big) nd_out[r] = mine;
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t k = 0; k < kRowsPerThread; ++k) {
+        const uint32_t j = threadIdx.x + k * kThreads;
+        if (j < nrows && rcnt[j] != kNotCounted) nd_out[r_lo + j] = rcnt[j];
+        if (slot[k] < max_big) big_list[slot[k]] = r_lo + j;  // always, unless rowptr is malformed
     }
 }
 
@@ -252,7 +319,8 @@ __global__ __launch_bounds__(kParts) void k_nbr_final(const double *__restrict__
 
 struct NbrLayout {
     uint32_t nchunk = 0, parts = 0, per_part = 0, max_big = 0;
-    uint32_t *chunk_row = nullptr, *nd = nullptr, *big_list = nullptr, *big_count = nullptr, *part_cnt = nullptr;
+    uint2 *chunk = nullptr;
+    uint32_t *nd = nullptr, *big_list = nullptr, *big_count = nullptr, *part_cnt = nullptr;
     double *part_sum = nullptr;
     size_t bytes = 0;
 };
@@ -265,7 +333,7 @@ NbrLayout nbr_layout(void *ws, int64_t n_rows, int64_t nnz) {
     L.parts = n_rows > 0 ? ceil_div((uint64_t)n_rows, L.per_part) : 0;
     L.max_big = (uint32_t)((uint64_t)nnz / (kSmall + 1) + 1);
     Carver c(ws);
-    L.chunk_row = c.take<uint32_t>(L.nchunk + 1ull);
+    L.chunk = c.take<uint2>(L.nchunk + 1ull);
     L.nd = c.take<uint32_t>((size_t)n_rows);
     L.big_list = c.take<uint32_t>(L.max_big);
     L.big_count = c.take<uint32_t>(1);
@@ -309,9 +377,9 @@ extern "C" boba_status boba_nbr(const int32_t *rowptr, const int32_t *col, int64
     uint32_t *nd = lines_per_row ? (uint32_t *)lines_per_row : L.nd;
     if (nr > 0) {
         BOBA_LAUNCH("nbr_split", k_nbr_split, dim3(ceil_div(L.nchunk + 1ull, kThreads)), dim3(kThreads), stream,
-                    rowptr, nr, ne, L.nchunk, L.chunk_row, L.big_count);
+                    rowptr, nr, ne, L.nchunk, L.chunk, L.big_count);
         BOBA_LAUNCH("nbr_chunk", k_nbr_chunk, dim3(L.nchunk), dim3(kThreads), stream, rowptr, col, nc, ne, shift,
-                    (const uint32_t *)L.chunk_row, nd, L.big_list, L.max_big, L.big_count, flag);
+                    (const uint2 *)L.chunk, nd, L.big_list, L.max_big, L.big_count, flag);
         // a bitmap over all lines when they fit in 128 KB (2^20 lines), so
         // that smaller ones let two or more workgroups share a CU
         const uint64_t nlines = ((uint64_t)nc + (uint64_t)line_ids - 1) >> shift;
