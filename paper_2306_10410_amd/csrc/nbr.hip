@@ -32,6 +32,8 @@ constexpr uint32_t kSmall = 256;                  // longest row a wavefront cou
 constexpr uint32_t kWin = kChunkE + kSmall;       // entries a chunk stages
 constexpr uint32_t kPerThread = kWin / kThreads;  // staged entries per thread in the row scan
 constexpr uint32_t kRowsPerThread = kChunkE / kThreads;  // rows of a chunk per thread
+constexpr uint32_t kLists = kWave;                // lists of rows longer than kSmall
+constexpr uint32_t kBigPerChunk = (kChunkE + kSmall + 1) / (kSmall + 2);  // ceil(kChunkE / (kSmall + 2))
 constexpr uint32_t kNotCounted = 0xFFFFFFFFu;     // count slot of rows the chunk does not count
 constexpr uint32_t kTableBits = 12;               // hash set of a chunk's (row, line) pairs
 constexpr uint32_t kTable = 1u << kTableBits;
@@ -48,12 +50,12 @@ __device__ __forceinline__ uint32_t clamp_ptr(int32_t p, uint32_t nnz) {
 }
 
 // chunk[c] = {r, rowptr[r]} for the first row r with r + rowptr[r] >=
-// c * kChunkE (r = n_rows for c = nchunk); also clears the big-row counter.
+// c * kChunkE (r = n_rows for c = nchunk); also clears the big-row counters.
 __global__ __launch_bounds__(kThreads) void k_nbr_split(const int32_t *__restrict__ rowptr, uint32_t n_rows,
                                                         uint32_t nnz, uint32_t nchunk, uint2 *__restrict__ chunk,
                                                         uint32_t *__restrict__ big_count) {
     const uint32_t c = blockIdx.x * kThreads + threadIdx.x;
-    if (c == 0) *big_count = 0;
+    if (c < kLists) big_count[c] = 0;
     if (c > nchunk) return;
     uint32_t lo = 0, hi = n_rows;
     if (c == nchunk) {
@@ -74,13 +76,14 @@ __global__ __launch_bounds__(kThreads) void k_nbr_chunk(const int32_t *__restric
                                                         uint32_t nnz, uint32_t shift,
                                                         const uint2 *__restrict__ chunk,
                                                         uint32_t *__restrict__ nd_out,
-                                                        uint32_t *__restrict__ big_list, uint32_t max_big,
+                                                        uint32_t *__restrict__ big_list, uint32_t per_list,
                                                         uint32_t *__restrict__ big_count, int32_t *flag) {
     __shared__ uint32_t lines[kWin];
     __shared__ uint16_t rowof[kWin];      // 1 + the chunk-local row of each staged entry (0: none)
     __shared__ uint32_t rcnt[kChunkE];    // distinct lines of each counted row; kNotCounted for the others
     __shared__ uint32_t table[kTable];    // hash set of (row, line): the staged entry that holds the pair
     __shared__ uint32_t red[kThreads / kWave];
+    __shared__ uint32_t big_at[2];        // the chunk's listed rows, and their first slot in the list
     const uint2 first = chunk[blockIdx.x], next = chunk[blockIdx.x + 1];
     const uint32_t r_lo = first.x, r_hi = next.x;
     if (r_lo >= r_hi) return;
@@ -115,10 +118,12 @@ __global__ __launch_bounds__(kThreads) void k_nbr_chunk(const int32_t *__restric
         rowof[i] = 0;
     }
     for (uint32_t h = threadIdx.x; h < kTable; h += kThreads) table[h] = kEmpty;
+    if (threadIdx.x == 0) big_at[0] = 0;
     __syncthreads();
-    // rows longer than kSmall go on the list (stored at the end, so that the
-    // counter's reply is not waited for here), empty ones get 0, the others
-    // mark their first entry
+    // rows longer than kSmall go on list c mod kLists (one counter update
+    // per chunk, whose reply is not waited for until the end; kLists
+    // counters, so that the updates of neighbouring chunks do not queue on
+    // one address), empty ones get 0, the others mark their first entry
     uint32_t slot[kRowsPerThread];
 #pragma unroll
     for (uint32_t k = 0; k < kRowsPerThread; ++k) {
@@ -126,24 +131,26 @@ __global__ __launch_bounds__(kThreads) void k_nbr_chunk(const int32_t *__restric
         const bool ok = j < nrows;
         const uint32_t d = e[k] > s[k] ? e[k] - s[k] : 0u;
         const bool big = ok && d > kSmall;
-        slot[k] = big ? atomicAdd(big_count, 1u) : ~0u;
+        slot[k] = big ? atomicAdd(&big_at[0], 1u) : ~0u;
         const bool staged = ok && d > 0 && s[k] >= base && s[k] - base < cnt;
         const bool counted = staged && !big && s[k] - base + d <= cnt;
         if (staged) rowof[s[k] - base] = (uint16_t)(j + 1);  // listed rows too: their entries are skipped
         if (ok) rcnt[j] = counted ? 0u : kNotCounted;
         if (ok && !big && !counted) nd_out[r_lo + j] = 0;
     }
-    for (uint32_t j = kChunkE + threadIdx.x; j < nrows; j += kThreads) {
+    for (uint32_t j = kChunkE + threadIdx.x; j < nrows; j += kThreads) {  // malformed rowptr only
         const uint32_t r = r_lo + j;
         const uint32_t rs = clamp_ptr(rowptr[r], nnz), re = clamp_ptr(rowptr[r + 1], nnz);
         if (re > rs && re - rs > kSmall) {
-            const uint32_t i = atomicAdd(big_count, 1u);
-            if (i < max_big) big_list[i] = r;
+            const uint32_t i = atomicAdd(&big_count[blockIdx.x % kLists], 1u);
+            if (i < per_list) big_list[(blockIdx.x % kLists) * per_list + i] = r;
         } else {
             nd_out[r] = 0;
         }
     }
     __syncthreads();
+    uint32_t list_base = 0;
+    if (threadIdx.x == 0 && big_at[0] > 0) list_base = atomicAdd(&big_count[blockIdx.x % kLists], big_at[0]);
     // the row of entry i is the last row marked at or before i (max-scan)
     {
         uint32_t loc[kPerThread], m = 0;
@@ -198,12 +205,14 @@ __global__ __launch_bounds__(kThreads) void k_nbr_chunk(const int32_t *__restric
             if (n) atomicAdd(&rcnt[j1 - 1], n);
         }
     }
+    if (threadIdx.x == 0) big_at[1] = list_base;
     __syncthreads();
 #pragma unroll
     for (uint32_t k = 0; k < kRowsPerThread; ++k) {
         const uint32_t j = threadIdx.x + k * kThreads;
         if (j < nrows && rcnt[j] != kNotCounted) nd_out[r_lo + j] = rcnt[j];
-        if (slot[k] < max_big) big_list[slot[k]] = r_lo + j;  // always, unless rowptr is malformed
+        if (slot[k] != ~0u && big_at[1] + slot[k] < per_list)  // always, unless rowptr is malformed
+            big_list[(blockIdx.x % kLists) * per_list + big_at[1] + slot[k]] = r_lo + j;
     }
 }
 
@@ -214,15 +223,29 @@ __global__ __launch_bounds__(kThreads) void k_nbr_chunk(const int32_t *__restric
 __global__ __launch_bounds__(kBigThreads) void k_nbr_big(const int32_t *__restrict__ rowptr,
                                                          const int32_t *__restrict__ col, uint32_t n_cols,
                                                          uint32_t nnz, uint32_t shift, uint32_t words, bool whole,
-                                                         const uint32_t *__restrict__ big_list, uint32_t max_big,
+                                                         const uint32_t *__restrict__ big_list, uint32_t per_list,
                                                          const uint32_t *__restrict__ big_count,
                                                          uint32_t *__restrict__ nd_out, int32_t *flag) {
     extern __shared__ uint32_t bm[];
     __shared__ uint32_t red[kBigThreads / kWave];
-    const uint32_t nbig = min(*big_count, max_big);
+    // the lists interleaved (visit v is entry v / kLists of list v % kLists),
+    // which is about the order of the chunks that filled them: the rows of
+    // the first chunks, BOBA's hubs, are handed out first
+    __shared__ uint32_t len[kLists];
+    __shared__ uint32_t longest;
+    if (threadIdx.x < kWave) {
+        const uint32_t n = min(big_count[threadIdx.x], per_list);
+        len[threadIdx.x] = n;
+        const uint32_t m = wave_reduce(n, OpMax{});
+        if (threadIdx.x == 0) longest = m;
+    }
+    __syncthreads();
+    const uint64_t visits = (uint64_t)kLists * longest;
     const uint64_t cover = 32ull * words;
-    for (uint32_t i = blockIdx.x; i < nbig; i += gridDim.x) {
-        const uint32_t r = big_list[i];
+    for (uint64_t vi = blockIdx.x; vi < visits; vi += gridDim.x) {
+        const uint32_t l = (uint32_t)(vi % kLists), p = (uint32_t)(vi / kLists);
+        if (p >= len[l]) continue;  // the same for the whole workgroup
+        const uint32_t r = big_list[(size_t)l * per_list + p];
         const uint32_t s = clamp_ptr(rowptr[r], nnz), e = max(s, clamp_ptr(rowptr[r + 1], nnz));
         uint64_t lo = 0, hi = cover - 1;
         if (!whole) {
@@ -318,7 +341,7 @@ __global__ __launch_bounds__(kParts) void k_nbr_final(const double *__restrict__
 }
 
 struct NbrLayout {
-    uint32_t nchunk = 0, parts = 0, per_part = 0, max_big = 0;
+    uint32_t nchunk = 0, parts = 0, per_part = 0, max_big = 0, per_list = 0;
     uint2 *chunk = nullptr;
     uint32_t *nd = nullptr, *big_list = nullptr, *big_count = nullptr, *part_cnt = nullptr;
     double *part_sum = nullptr;
@@ -335,8 +358,11 @@ NbrLayout nbr_layout(void *ws, int64_t n_rows, int64_t nnz) {
     Carver c(ws);
     L.chunk = c.take<uint2>(L.nchunk + 1ull);
     L.nd = c.take<uint32_t>((size_t)n_rows);
-    L.big_list = c.take<uint32_t>(L.max_big);
-    L.big_count = c.take<uint32_t>(1);
+    // a chunk holds at most kBigPerChunk rows longer than kSmall: their first
+    // items lie more than kSmall + 1 apart
+    L.per_list = (uint32_t)std::min<uint64_t>(L.max_big, (uint64_t)kBigPerChunk * ceil_div(L.nchunk, kLists));
+    L.big_list = c.take<uint32_t>((size_t)kLists * L.per_list);
+    L.big_count = c.take<uint32_t>(kLists);
     L.part_sum = c.take<double>(kParts);
     L.part_cnt = c.take<uint32_t>(kParts);
     L.bytes = c.bytes();
@@ -379,7 +405,7 @@ extern "C" boba_status boba_nbr(const int32_t *rowptr, const int32_t *col, int64
         BOBA_LAUNCH("nbr_split", k_nbr_split, dim3(ceil_div(L.nchunk + 1ull, kThreads)), dim3(kThreads), stream,
                     rowptr, nr, ne, L.nchunk, L.chunk, L.big_count);
         BOBA_LAUNCH("nbr_chunk", k_nbr_chunk, dim3(L.nchunk), dim3(kThreads), stream, rowptr, col, nc, ne, shift,
-                    (const uint2 *)L.chunk, nd, L.big_list, L.max_big, L.big_count, flag);
+                    (const uint2 *)L.chunk, nd, L.big_list, L.per_list, L.big_count, flag);
         // a bitmap over all lines when they fit in 128 KB (2^20 lines), so
         // that smaller ones let two or more workgroups share a CU
         const uint64_t nlines = ((uint64_t)nc + (uint64_t)line_ids - 1) >> shift;
@@ -389,7 +415,7 @@ extern "C" boba_status boba_nbr(const int32_t *rowptr, const int32_t *col, int64
         const uint32_t grid_big = std::min<uint64_t>(L.max_big, (uint64_t)device_cus() * per_cu);
         const int tok = timing_begin("nbr_big", stream);
         hipLaunchKernelGGL(k_nbr_big, dim3(grid_big), dim3(kBigThreads), 4ull * words, stream, rowptr, col, nc, ne,
-                           shift, words, whole, (const uint32_t *)L.big_list, L.max_big,
+                           shift, words, whole, (const uint32_t *)L.big_list, L.per_list,
                            (const uint32_t *)L.big_count, nd, flag);
         timing_end(tok, stream);
         if (boba_status e = check_launch("nbr_big")) return e;
