@@ -12,11 +12,13 @@
 //           hash set (the insertion that finds the pair absent is a new
 //           line), and the first lane of each row's run in a wavefront adds
 //           the run's new lines to the row's count.  Rows longer than kSmall
-//           are put on a list.
-//   big     a workgroup per listed row with an LDS bitmap: over all lines in
-//           one pass when they number at most 2^20, else one pass per 2^20
-//           lines of the row's [min, max] line span; an entry is new when its
-//           bit was clear.
+//           are put on lists, by length.
+//   mid     a workgroup per listed row of up to kMid entries with an LDS hash
+//           set of its lines; the insertion that finds a line absent counts.
+//   big     a workgroup per longer listed row with an LDS bitmap: over all
+//           lines in one pass when they number at most 2^20, else one pass
+//           per 2^20 lines of the row's [min, max] line span; an entry is new
+//           when its bit was clear.
 //   reduce  the per-row ratios summed in a fixed order (per part of the rows,
 //           then over the parts), so the result is bit-reproducible.
 #include <algorithm>
@@ -34,6 +36,10 @@ constexpr uint32_t kPerThread = kWin / kThreads;  // staged entries per thread i
 constexpr uint32_t kRowsPerThread = kChunkE / kThreads;  // rows of a chunk per thread
 constexpr uint32_t kLists = kWave;                // lists of rows longer than kSmall
 constexpr uint32_t kBigPerChunk = (kChunkE + kSmall + 1) / (kSmall + 2);  // ceil(kChunkE / (kSmall + 2))
+constexpr uint32_t kMid = 2048;                   // longest row the hash-set kernel counts
+constexpr uint32_t kMidThreads = 256;
+constexpr uint32_t kMidTableBits = 12;            // 4096 slots: at most half full
+constexpr uint32_t kMidTable = 1u << kMidTableBits;
 constexpr uint32_t kNotCounted = 0xFFFFFFFFu;     // count slot of rows the chunk does not count
 constexpr uint32_t kTableBits = 12;               // hash set of a chunk's (row, line) pairs
 constexpr uint32_t kTable = 1u << kTableBits;
@@ -53,9 +59,9 @@ __device__ __forceinline__ uint32_t clamp_ptr(int32_t p, uint32_t nnz) {
 // c * kChunkE (r = n_rows for c = nchunk); also clears the big-row counters.
 __global__ __launch_bounds__(kThreads) void k_nbr_split(const int32_t *__restrict__ rowptr, uint32_t n_rows,
                                                         uint32_t nnz, uint32_t nchunk, uint2 *__restrict__ chunk,
-                                                        uint32_t *__restrict__ big_count) {
+                                                        uint32_t *__restrict__ list_count) {
     const uint32_t c = blockIdx.x * kThreads + threadIdx.x;
-    if (c < kLists) big_count[c] = 0;
+    if (c < 2 * kLists) list_count[c] = 0;
     if (c > nchunk) return;
     uint32_t lo = 0, hi = n_rows;
     if (c == nchunk) {
@@ -76,14 +82,14 @@ __global__ __launch_bounds__(kThreads) void k_nbr_chunk(const int32_t *__restric
                                                         uint32_t nnz, uint32_t shift,
                                                         const uint2 *__restrict__ chunk,
                                                         uint32_t *__restrict__ nd_out,
-                                                        uint32_t *__restrict__ big_list, uint32_t per_list,
-                                                        uint32_t *__restrict__ big_count, int32_t *flag) {
+                                                        uint32_t *__restrict__ lists, uint32_t per_list,
+                                                        uint32_t *__restrict__ list_count, int32_t *flag) {
     __shared__ uint32_t lines[kWin];
     __shared__ uint16_t rowof[kWin];      // 1 + the chunk-local row of each staged entry (0: none)
     __shared__ uint32_t rcnt[kChunkE];    // distinct lines of each counted row; kNotCounted for the others
     __shared__ uint32_t table[kTable];    // hash set of (row, line): the staged entry that holds the pair
     __shared__ uint32_t red[kThreads / kWave];
-    __shared__ uint32_t big_at[2];        // the chunk's listed rows, and their first slot in the list
+    __shared__ uint32_t list_at[4];       // the chunk's listed rows per class, and their first slots
     const uint2 first = chunk[blockIdx.x], next = chunk[blockIdx.x + 1];
     const uint32_t r_lo = first.x, r_hi = next.x;
     if (r_lo >= r_hi) return;
@@ -118,12 +124,14 @@ __global__ __launch_bounds__(kThreads) void k_nbr_chunk(const int32_t *__restric
         rowof[i] = 0;
     }
     for (uint32_t h = threadIdx.x; h < kTable; h += kThreads) table[h] = kEmpty;
-    if (threadIdx.x == 0) big_at[0] = 0;
+    if (threadIdx.x < 2) list_at[threadIdx.x] = 0;
     __syncthreads();
-    // rows longer than kSmall go on list c mod kLists (one counter update
-    // per chunk, whose reply is not waited for until the end; kLists
-    // counters, so that the updates of neighbouring chunks do not queue on
-    // one address), empty ones get 0, the others mark their first entry
+    // rows longer than kSmall go on list c mod kLists of their class (up to
+    // kMid entries: class 0, the hash-set kernel's; longer: class 1, the
+    // bitmap kernel's), with one counter update per class and chunk whose
+    // reply is not waited for until the end (kLists counters, so that the
+    // updates of neighbouring chunks do not queue on one address); empty
+    // rows get 0, the others mark their first entry
     uint32_t slot[kRowsPerThread];
 #pragma unroll
     for (uint32_t k = 0; k < kRowsPerThread; ++k) {
@@ -131,7 +139,8 @@ __global__ __launch_bounds__(kThreads) void k_nbr_chunk(const int32_t *__restric
         const bool ok = j < nrows;
         const uint32_t d = e[k] > s[k] ? e[k] - s[k] : 0u;
         const bool big = ok && d > kSmall;
-        slot[k] = big ? atomicAdd(&big_at[0], 1u) : ~0u;
+        const uint32_t cls = d > kMid;
+        slot[k] = big ? (cls << 31) | atomicAdd(&list_at[cls], 1u) : ~0u;
         const bool staged = ok && d > 0 && s[k] >= base && s[k] - base < cnt;
         const bool counted = staged && !big && s[k] - base + d <= cnt;
         if (staged) rowof[s[k] - base] = (uint16_t)(j + 1);  // listed rows too: their entries are skipped
@@ -142,15 +151,19 @@ __global__ __launch_bounds__(kThreads) void k_nbr_chunk(const int32_t *__restric
         const uint32_t r = r_lo + j;
         const uint32_t rs = clamp_ptr(rowptr[r], nnz), re = clamp_ptr(rowptr[r + 1], nnz);
         if (re > rs && re - rs > kSmall) {
-            const uint32_t i = atomicAdd(&big_count[blockIdx.x % kLists], 1u);
-            if (i < per_list) big_list[(blockIdx.x % kLists) * per_list + i] = r;
+            const uint32_t li = (re - rs > kMid) * kLists + blockIdx.x % kLists;
+            const uint32_t i = atomicAdd(&list_count[li], 1u);
+            if (i < per_list) lists[(size_t)li * per_list + i] = r;
         } else {
             nd_out[r] = 0;
         }
     }
     __syncthreads();
-    uint32_t list_base = 0;
-    if (threadIdx.x == 0 && big_at[0] > 0) list_base = atomicAdd(&big_count[blockIdx.x % kLists], big_at[0]);
+    uint32_t base0 = 0, base1 = 0;
+    if (threadIdx.x == 0) {
+        if (list_at[0] > 0) base0 = atomicAdd(&list_count[blockIdx.x % kLists], list_at[0]);
+        if (list_at[1] > 0) base1 = atomicAdd(&list_count[kLists + blockIdx.x % kLists], list_at[1]);
+    }
     // the row of entry i is the last row marked at or before i (max-scan)
     {
         uint32_t loc[kPerThread], m = 0;
@@ -205,21 +218,93 @@ __global__ __launch_bounds__(kThreads) void k_nbr_chunk(const int32_t *__restric
             if (n) atomicAdd(&rcnt[j1 - 1], n);
         }
     }
-    if (threadIdx.x == 0) big_at[1] = list_base;
+    if (threadIdx.x == 0) {
+        list_at[2] = base0;
+        list_at[3] = base1;
+    }
     __syncthreads();
 #pragma unroll
     for (uint32_t k = 0; k < kRowsPerThread; ++k) {
         const uint32_t j = threadIdx.x + k * kThreads;
         if (j < nrows && rcnt[j] != kNotCounted) nd_out[r_lo + j] = rcnt[j];
-        if (slot[k] != ~0u && big_at[1] + slot[k] < per_list)  // always, unless rowptr is malformed
-            big_list[(blockIdx.x % kLists) * per_list + big_at[1] + slot[k]] = r_lo + j;
+        if (slot[k] != ~0u) {
+            const uint32_t cls = slot[k] >> 31, at = list_at[2 + cls] + (slot[k] & 0x7FFFFFFFu);
+            if (at < per_list)  // always, unless rowptr is malformed
+                lists[(size_t)(cls * kLists + blockIdx.x % kLists) * per_list + at] = r_lo + j;
+        }
     }
 }
 
-// A workgroup per listed row.  The bitmap (dynamic LDS, `words` words) covers
-// lines [p0, p0 + 32*words).  When all lines fit (`whole`), one pass over
-// [0, 32*words) serves every row; otherwise the row's [min, max] line span is
-// found first and covered in as many passes as it takes.
+// The lengths of the kLists lists of one class (read by the first
+// wavefront) and the number of visits that covers the longest.  Visit v is
+// entry v / kLists of list v % kLists: about the order of the chunks that
+// filled the lists, so the rows of the first chunks, BOBA's hubs, are handed
+// out first.  Every thread of the workgroup calls it.
+__device__ uint64_t list_visits(const uint32_t *__restrict__ counts, uint32_t per_list, uint32_t *len,
+                                uint32_t *longest) {
+    if (threadIdx.x < kWave) {
+        const uint32_t n = min(counts[threadIdx.x], per_list);
+        len[threadIdx.x] = n;
+        const uint32_t m = wave_reduce(n, OpMax{});
+        if (threadIdx.x == 0) *longest = m;
+    }
+    __syncthreads();
+    return (uint64_t)kLists * *longest;
+}
+
+// A workgroup per listed row of kSmall < d <= kMid entries: the row's lines
+// go into an LDS hash set (linear probing, compare-and-swap of the line);
+// the insertion that finds the line absent counts it.
+__global__ __launch_bounds__(kMidThreads) void k_nbr_mid(const int32_t *__restrict__ rowptr,
+                                                         const int32_t *__restrict__ col, uint32_t n_cols,
+                                                         uint32_t nnz, uint32_t shift,
+                                                         const uint32_t *__restrict__ list, uint32_t per_list,
+                                                         const uint32_t *__restrict__ counts,
+                                                         uint32_t *__restrict__ nd_out, int32_t *flag) {
+    __shared__ uint32_t tab[kMidTable];
+    __shared__ uint32_t red[kMidThreads / kWave];
+    __shared__ uint32_t len[kLists];
+    __shared__ uint32_t longest;
+    const uint64_t visits = list_visits(counts, per_list, len, &longest);
+    for (uint64_t vi = blockIdx.x; vi < visits; vi += gridDim.x) {
+        const uint32_t l = (uint32_t)(vi % kLists), p = (uint32_t)(vi / kLists);
+        if (p >= len[l]) continue;  // the same for the whole workgroup
+        const uint32_t r = list[(size_t)l * per_list + p];
+        const uint32_t s = clamp_ptr(rowptr[r], nnz);
+        // at most kMid < kMidTable insertions, so a free slot is always left
+        const uint32_t e = min(max(s, clamp_ptr(rowptr[r + 1], nnz)), s + kMid);
+        for (uint32_t h = threadIdx.x; h < kMidTable; h += kMidThreads) tab[h] = kEmpty;
+        __syncthreads();
+        uint32_t fresh = 0;
+        for (uint32_t k = s + threadIdx.x; k < e; k += kMidThreads) {
+            const uint32_t v = (uint32_t)col[k];
+            if (v >= n_cols) {
+                flag_range_error(flag);
+                continue;
+            }
+            const uint32_t line = v >> shift;  // < 2^31, never kEmpty
+            uint32_t h = (line * 0x9E3779B1u) >> (32 - kMidTableBits);
+            for (;;) {
+                const uint32_t old = atomicCAS(&tab[h], kEmpty, line);
+                if (old == kEmpty) {
+                    ++fresh;
+                    break;
+                }
+                if (old == line) break;
+                h = (h + 1) & (kMidTable - 1);
+            }
+        }
+        // (its first barrier also keeps the next row's clearing after every insertion)
+        const uint32_t nd = block_reduce<kMidThreads>(fresh, OpSum{}, red);
+        if (threadIdx.x == 0) nd_out[r] = nd;
+    }
+}
+
+// A workgroup per listed row longer than kMid.  The bitmap (dynamic LDS,
+// `words` words) covers lines [p0, p0 + 32*words).  When all lines fit
+// (`whole`), one pass over [0, 32*words) serves every row; otherwise the
+// row's [min, max] line span is found first and covered in as many passes as
+// it takes.
 __global__ __launch_bounds__(kBigThreads) void k_nbr_big(const int32_t *__restrict__ rowptr,
                                                          const int32_t *__restrict__ col, uint32_t n_cols,
                                                          uint32_t nnz, uint32_t shift, uint32_t words, bool whole,
@@ -228,19 +313,9 @@ __global__ __launch_bounds__(kBigThreads) void k_nbr_big(const int32_t *__restri
                                                          uint32_t *__restrict__ nd_out, int32_t *flag) {
     extern __shared__ uint32_t bm[];
     __shared__ uint32_t red[kBigThreads / kWave];
-    // the lists interleaved (visit v is entry v / kLists of list v % kLists),
-    // which is about the order of the chunks that filled them: the rows of
-    // the first chunks, BOBA's hubs, are handed out first
     __shared__ uint32_t len[kLists];
     __shared__ uint32_t longest;
-    if (threadIdx.x < kWave) {
-        const uint32_t n = min(big_count[threadIdx.x], per_list);
-        len[threadIdx.x] = n;
-        const uint32_t m = wave_reduce(n, OpMax{});
-        if (threadIdx.x == 0) longest = m;
-    }
-    __syncthreads();
-    const uint64_t visits = (uint64_t)kLists * longest;
+    const uint64_t visits = list_visits(big_count, per_list, len, &longest);
     const uint64_t cover = 32ull * words;
     for (uint64_t vi = blockIdx.x; vi < visits; vi += gridDim.x) {
         const uint32_t l = (uint32_t)(vi % kLists), p = (uint32_t)(vi / kLists);
@@ -343,7 +418,7 @@ __global__ __launch_bounds__(kParts) void k_nbr_final(const double *__restrict__
 struct NbrLayout {
     uint32_t nchunk = 0, parts = 0, per_part = 0, max_big = 0, per_list = 0;
     uint2 *chunk = nullptr;
-    uint32_t *nd = nullptr, *big_list = nullptr, *big_count = nullptr, *part_cnt = nullptr;
+    uint32_t *nd = nullptr, *lists = nullptr, *list_count = nullptr, *part_cnt = nullptr;
     double *part_sum = nullptr;
     size_t bytes = 0;
 };
@@ -361,8 +436,8 @@ NbrLayout nbr_layout(void *ws, int64_t n_rows, int64_t nnz) {
     // a chunk holds at most kBigPerChunk rows longer than kSmall: their first
     // items lie more than kSmall + 1 apart
     L.per_list = (uint32_t)std::min<uint64_t>(L.max_big, (uint64_t)kBigPerChunk * ceil_div(L.nchunk, kLists));
-    L.big_list = c.take<uint32_t>((size_t)kLists * L.per_list);
-    L.big_count = c.take<uint32_t>(kLists);
+    L.lists = c.take<uint32_t>(2ull * kLists * L.per_list);  // class 0 (kSmall < d <= kMid), then class 1
+    L.list_count = c.take<uint32_t>(2 * kLists);
     L.part_sum = c.take<double>(kParts);
     L.part_cnt = c.take<uint32_t>(kParts);
     L.bytes = c.bytes();
@@ -403,9 +478,12 @@ extern "C" boba_status boba_nbr(const int32_t *rowptr, const int32_t *col, int64
     uint32_t *nd = lines_per_row ? (uint32_t *)lines_per_row : L.nd;
     if (nr > 0) {
         BOBA_LAUNCH("nbr_split", k_nbr_split, dim3(ceil_div(L.nchunk + 1ull, kThreads)), dim3(kThreads), stream,
-                    rowptr, nr, ne, L.nchunk, L.chunk, L.big_count);
+                    rowptr, nr, ne, L.nchunk, L.chunk, L.list_count);
         BOBA_LAUNCH("nbr_chunk", k_nbr_chunk, dim3(L.nchunk), dim3(kThreads), stream, rowptr, col, nc, ne, shift,
-                    (const uint2 *)L.chunk, nd, L.big_list, L.per_list, L.big_count, flag);
+                    (const uint2 *)L.chunk, nd, L.lists, L.per_list, L.list_count, flag);
+        const uint32_t grid_mid = std::max<uint64_t>(1, std::min<uint64_t>(L.max_big, (uint64_t)device_cus() * 8));
+        BOBA_LAUNCH("nbr_mid", k_nbr_mid, dim3(grid_mid), dim3(kMidThreads), stream, rowptr, col, nc, ne, shift,
+                    (const uint32_t *)L.lists, L.per_list, (const uint32_t *)L.list_count, nd, flag);
         // a bitmap over all lines when they fit in 128 KB (2^20 lines), so
         // that smaller ones let two or more workgroups share a CU
         const uint64_t nlines = ((uint64_t)nc + (uint64_t)line_ids - 1) >> shift;
@@ -415,8 +493,8 @@ extern "C" boba_status boba_nbr(const int32_t *rowptr, const int32_t *col, int64
         const uint32_t grid_big = std::min<uint64_t>(L.max_big, (uint64_t)device_cus() * per_cu);
         const int tok = timing_begin("nbr_big", stream);
         hipLaunchKernelGGL(k_nbr_big, dim3(grid_big), dim3(kBigThreads), 4ull * words, stream, rowptr, col, nc, ne,
-                           shift, words, whole, (const uint32_t *)L.big_list, L.per_list,
-                           (const uint32_t *)L.big_count, nd, flag);
+                           shift, words, whole, (const uint32_t *)L.lists + (size_t)kLists * L.per_list,
+                           L.per_list, (const uint32_t *)L.list_count + kLists, nd, flag);
         timing_end(tok, stream);
         if (boba_status e = check_launch("nbr_big")) return e;
         BOBA_LAUNCH("nbr_reduce", k_nbr_reduce, dim3(L.parts), dim3(kThreads), stream, rowptr, nr, ne, L.per_part,

@@ -49,6 +49,26 @@ def test_rows_around_the_wavefront_limit_and_chunk_edges():
     nbr_check(rowptr, col, n, line_ids=1)
 
 
+def test_rows_around_the_hash_set_limit():
+    # rows of 2047..2050 entries straddle the longest row counted with a hash
+    # set (longer ones take the bitmap); one draws from ~125 lines, one gives
+    # about a line per entry, and 257 and 3000 entries sit inside each class
+    rng = np.random.default_rng(101)
+    deg = np.array([2047, 2048, 2049, 2050, 300, 1000, 5, 0, 3000, 257])
+    rowptr = np.concatenate([[0], np.cumsum(deg)]).astype(np.int32)
+    n = 1 << 20
+    col = rng.integers(0, n, rowptr[-1]).astype(np.int32)
+    col[rowptr[0]:rowptr[1]] = rng.integers(0, 4000, deg[0])
+    col[rowptr[2]:rowptr[3]] = rng.integers(0, 70000, deg[2])
+    nbr_check(rowptr, col, n)
+    nbr_check(rowptr, col, n, line_ids=1)
+    # an out-of-range column inside a row counted with the bitmap
+    col[rowptr[8] + 100] = n + 5
+    assert boba.boba_check_device_error() == boba.BOBA_OK
+    boba.boba_nbr(dev(rowptr), dev(col), n)
+    assert boba.boba_check_device_error() == boba.BOBA_ERR_RANGE
+
+
 def test_long_runs_of_empty_rows():
     # chunks count rows as well as entries: 100,000 empty rows in the middle
     # and 200,000 at the end (where BOBA puts isolated vertices) are shared
