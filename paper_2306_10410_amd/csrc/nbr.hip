@@ -29,7 +29,7 @@ namespace boba {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr uint32_t kChunkE = 2048;                // items (rows + entries) per chunk
+constexpr uint32_t kChunkE = 1024;                // items (rows + entries) per chunk
 constexpr uint32_t kSmall = 256;                  // longest row a wavefront counts
 constexpr uint32_t kWin = kChunkE + kSmall;       // entries a chunk stages
 constexpr uint32_t kPerThread = kWin / kThreads;  // staged entries per thread in the row scan
@@ -41,7 +41,7 @@ constexpr uint32_t kMidThreads = 256;
 constexpr uint32_t kMidTableBits = 12;            // 4096 slots: at most half full
 constexpr uint32_t kMidTable = 1u << kMidTableBits;
 constexpr uint32_t kNotCounted = 0xFFFFFFFFu;     // count slot of rows the chunk does not count
-constexpr uint32_t kTableBits = 12;               // hash set of a chunk's (row, line) pairs
+constexpr uint32_t kTableBits = 11;               // hash set of a chunk's (row, line) pairs
 constexpr uint32_t kTable = 1u << kTableBits;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 static_assert(kWin % kThreads == 0 && kChunkE % kThreads == 0 && kThreads % kWave == 0,

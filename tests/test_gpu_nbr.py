@@ -36,7 +36,7 @@ def test_line_widths(line_ids):
 
 def test_rows_around_the_wavefront_limit_and_chunk_edges():
     # degrees 255..258 straddle the longest row a wavefront counts; a run of
-    # 250-entry rows puts row starts at every offset of the 2048-entry chunks;
+    # 250-entry rows puts row starts at every offset of the 1024-item chunks;
     # empty rows in between and at the end
     rng = np.random.default_rng(97)
     deg = np.concatenate([[255, 256, 257, 258, 0, 1, 64, 65, 0], np.full(40, 250), rng.integers(0, 300, 400),
