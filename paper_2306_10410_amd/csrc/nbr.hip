@@ -101,18 +101,27 @@ __global__ __launch_bounds__(kThreads) void k_nbr_chunk(const int32_t *__restric
     // a chunk holds at most kChunkE rows (r + rowptr[r] grows with r); more
     // can only come from a malformed rowptr and are given 0 below
     const uint32_t nrows = r_hi - r_lo;
-    // every load of the window and of the rows' bounds in flight at once
+    // every load of the window and of the rows' bounds in flight at once:
+    // unconditional loads at clamped (always valid) indices, so that no
+    // branch makes one wait before the next is issued
     uint32_t v[kPerThread], s[kRowsPerThread], e[kRowsPerThread];
+    if (cnt > 0) {  // the same for the whole workgroup
 #pragma unroll
-    for (uint32_t k = 0; k < kPerThread; ++k) {
-        const uint32_t i = threadIdx.x + k * kThreads;
-        v[k] = i < cnt ? (uint32_t)col[base + i] : 0u;
+        for (uint32_t k = 0; k < kPerThread; ++k)
+            v[k] = (uint32_t)col[base + min(threadIdx.x + k * kThreads, cnt - 1)];
     }
+    int32_t ps[kRowsPerThread], pe[kRowsPerThread];
 #pragma unroll
     for (uint32_t k = 0; k < kRowsPerThread; ++k) {
         const uint32_t j = threadIdx.x + k * kThreads;
-        s[k] = j < nrows ? clamp_ptr(rowptr[r_lo + j], nnz) : 0u;
-        e[k] = j < nrows ? clamp_ptr(rowptr[r_lo + j + 1], nnz) : 0u;
+        ps[k] = rowptr[r_lo + min(j, nrows)];
+        pe[k] = rowptr[r_lo + min(j + 1, nrows)];
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kRowsPerThread; ++k) {
+        const bool ok = threadIdx.x + k * kThreads < nrows;
+        s[k] = ok ? clamp_ptr(ps[k], nnz) : 0u;
+        e[k] = ok ? clamp_ptr(pe[k], nnz) : 0u;
     }
 #pragma unroll
     for (uint32_t k = 0; k < kPerThread; ++k) {

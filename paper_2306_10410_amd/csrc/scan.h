@@ -22,12 +22,15 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_reduce(Load load, uint32_t 
     __shared__ uint32_t lds[kScanBlock / kWave];
     Op op;
     const uint32_t base = blockIdx.x * kScanTile + threadIdx.x;
+    // loads at clamped indices (count >= 1 in a launched workgroup), so that
+    // all of them are in flight before the first is waited for
+    uint32_t v[kScanItems];
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) v[j] = load(min(base + j * kScanBlock, count - 1));
     uint32_t acc = Op::identity;
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        uint32_t i = base + j * kScanBlock;
-        if (i < count) acc = op(acc, load(i));
-    }
+    for (int j = 0; j < kScanItems; ++j)
+        if (base + j * kScanBlock < count) acc = op(acc, v[j]);
     acc = block_reduce<kScanBlock>(acc, op, lds);
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
@@ -62,10 +65,10 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_down(Load load, Store store
     uint32_t carry = partial[blockIdx.x];
     uint32_t x[kScanItems];
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        uint32_t i = base + j * kScanBlock;
-        x[j] = i < count ? load(i) : Op::identity;
-    }
+    for (int j = 0; j < kScanItems; ++j) x[j] = load(min(base + j * kScanBlock, count - 1));
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j)
+        if (base + j * kScanBlock >= count) x[j] = Op::identity;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
         uint32_t total;
