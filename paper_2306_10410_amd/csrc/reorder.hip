@@ -813,11 +813,15 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_block(uint2 *__restrict__
     const bool one_pass = e1 - e0 <= U * kRankThreads;
     uint2 held[U];
     if (one_pass) {
+        // loads at clamped indices, the guard applied afterwards: all U in
+        // flight before the first is waited for
+        if (e1 > e0) {  // the same for the whole workgroup
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint32_t i = e0 + threadIdx.x + u * kRankThreads;
-            held[u] = i < e1 ? E[i] : make_uint2(base, 0u);
+            for (int u = 0; u < U; ++u) held[u] = E[min(e0 + threadIdx.x + u * kRankThreads, e1 - 1)];
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (e0 + threadIdx.x + u * kRankThreads >= e1) held[u] = make_uint2(base, 0u);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint32_t p = held[u].x - base;
