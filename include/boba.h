@@ -267,8 +267,9 @@ BOBA_API boba_status boba_pagerank(const int32_t *rowptr, const int32_t *col, co
  *                  rows = result[0] / result[1].  The sum is taken in a fixed
  *                  order (bit-reproducible).
  *   ws             at least boba_nbr_workspace(n_rows, nnz) bytes, 256-byte aligned.
- * Column IDs outside [0, n_cols) are skipped and flagged
- * (boba_check_device_error).
+ * Column IDs outside [0, n_cols) are flagged (boba_check_device_error); the
+ * counts of the rows holding them are then unspecified (never an access out
+ * of bounds).
  * Errors: ERR_ARG (NULL, line_ids), ERR_OVERFLOW (a size >= 2^31),
  * ERR_WORKSPACE, ERR_HIP. */
 BOBA_API size_t boba_nbr_workspace(int64_t n_rows, int64_t nnz);
