@@ -123,6 +123,25 @@ def test_out_of_range_columns_set_the_device_flag():
     assert boba.boba_check_device_error() == boba.BOBA_ERR_RANGE
 
 
+def test_malformed_row_pointers_stay_in_bounds():
+    # rowptr decreasing, negative and past nnz: offsets are clamped, so the
+    # counts are unspecified but every access stays in bounds; a valid call
+    # afterwards is exact again
+    rng = np.random.default_rng(102)
+    col = rng.integers(0, 50, 10).astype(np.int32)
+    rowptr = np.array([0, 5, 3, 100000, 2, -7, 10], np.int32)
+    over_n, over_ne = boba.boba_nbr(dev(rowptr), dev(col), 50)
+    assert np.isfinite(over_n) and np.isfinite(over_ne)
+    nnz = 5000
+    col = rng.integers(0, 3000, nnz).astype(np.int32)
+    rowptr = rng.integers(-5, nnz + 600, 20001).astype(np.int32)
+    rowptr[::7] = np.sort(rowptr[::7])  # stretches that look well formed, long rows among them
+    boba.boba_nbr(dev(rowptr), dev(col), 3000)
+    assert boba.boba_check_device_error() == boba.BOBA_OK
+    g = graphgen.small_workload("rmat", 1 << 14, 1 << 17, 103)
+    nbr_check(*csr_of(g.src, g.dst, g.n), g.n)
+
+
 def test_repeatable_bits():
     g = graphgen.small_workload("rmat", 1 << 16, 1 << 20, 99)
     rp, col = csr_of(g.src, g.dst, g.n)
