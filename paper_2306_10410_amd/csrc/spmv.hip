@@ -38,6 +38,7 @@ constexpr int kItems = 16;
 constexpr uint32_t kChunk = kThreads * kItems;  // nonzeros per chunk
 constexpr uint32_t kShort = 64;                  // longer segments: one wavefront each
 constexpr uint32_t kNoRow = 0xFFFFFFFFu;
+constexpr uint32_t kLongCap = kChunk / kShort + 1;  // disjoint rows of > kShort nonzeros in a chunk
 
 // Merge-path split of diagonal d = c * kChunk: the number i of row ends and
 // j = d - i of nonzeros that come before it, where row r ends after nonzero
@@ -89,7 +90,7 @@ __global__ __launch_bounds__(kThreads) void k_spmv_chunk(const int32_t *__restri
                                                          const uint32_t *__restrict__ skip) {
     if (skip && *skip) return;  // a converged PageRank iteration
     __shared__ float prod[kChunk];
-    __shared__ uint32_t long_rows[kChunk / kShort + 1];
+    __shared__ uint32_t long_rows[kLongCap];
     __shared__ uint32_t n_long;
     const uint32_t c = blockIdx.x;
     const uint32_t e0 = split_j[c];
@@ -140,8 +141,13 @@ __global__ __launch_bounds__(kThreads) void k_spmv_chunk(const int32_t *__restri
         const uint32_t sb = max(rb, e0), se = min(re, e1);
         if (r == open_row && sb >= se) continue;  // the open row has no entries here
         if (sb < se && se - sb > kShort) {
-            long_rows[atomicAdd(&n_long, 1u)] = r;
-            continue;
+            const uint32_t q = atomicAdd(&n_long, 1u);
+            if (q < kLongCap) {
+                long_rows[q] = r;
+                continue;
+            }
+            // more long rows than disjoint ones can be: only overlapping rows
+            // of a malformed rowptr get here, and are summed by this thread
         }
         float acc = 0.f;
         for (uint32_t k = sb; k < se; ++k) acc += prod[k - e0];
@@ -151,7 +157,7 @@ __global__ __launch_bounds__(kThreads) void k_spmv_chunk(const int32_t *__restri
 
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = threadIdx.x / kWave;
-    for (uint32_t q = wave; q < n_long; q += kThreads / kWave) {
+    for (uint32_t q = wave; q < min(n_long, kLongCap); q += kThreads / kWave) {
         const uint32_t r = long_rows[q];
         const uint32_t rb = (uint32_t)min(max(rowptr[r], 0), nnz), re = (uint32_t)min(max(rowptr[r + 1], 0), nnz);
         const uint32_t sb = max(rb, e0), se = min(re, e1);

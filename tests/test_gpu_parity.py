@@ -148,6 +148,29 @@ def test_csr_without_values_and_spmv_special_cases():
     assert bits_equal(host(y), host(x))
 
 
+def test_spmv_malformed_row_pointers_stay_in_bounds():
+    # rows that overlap (rowptr falling back to 0 again and again) put more
+    # long rows into a chunk than disjoint rows can be; decreasing, negative
+    # and past-nnz offsets are clamped: the sums are unspecified, every access
+    # stays in bounds, and a valid call afterwards is exact again
+    rng = np.random.default_rng(83)
+    nnz = 3 * 4096
+    col = dev(rng.integers(0, 1000, nnz).astype(np.int32))
+    x = dev(graphgen.uniform_values(1000, 84))
+    rp = np.zeros(5001, np.int32)
+    rp[1::2] = nnz  # rows 0, 2, 4, ... each span every nonzero
+    assert np.all(np.isfinite(host(boba.spmv_csr(dev(rp), col, None, x))))
+    rp = rng.integers(-5, nnz + 600, 20001).astype(np.int32)
+    y = boba.spmv_csr(dev(rp), col, dev(graphgen.uniform_values(nnz, 85)), x)
+    assert np.all(np.isfinite(host(y)))
+    assert boba.boba_check_device_error() == boba.BOBA_OK
+    n = 5000
+    xe = dev(graphgen.uniform_values(n, 86))
+    eye = torch.arange(n + 1, dtype=torch.int32, device="cuda")
+    y = boba.spmv_csr(eye, eye[:n].contiguous(), torch.ones(n, device="cuda"), xe)
+    assert bits_equal(host(y), host(xe))
+
+
 def test_spmv_permutation_equivariance():
     g = graphgen.small_workload("rmat", 1 << 14, 1 << 18, 82)
     s, d = dev(g.src), dev(g.dst)
