@@ -30,7 +30,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr uint32_t kChunkE = 1024;                // items (rows + entries) per chunk
-constexpr uint32_t kSmall = 256;                  // longest row a wavefront counts
+constexpr uint32_t kSmall = 256;                  // longest row the chunk kernel counts
 constexpr uint32_t kWin = kChunkE + kSmall;       // entries a chunk stages
 constexpr uint32_t kPerThread = kWin / kThreads;  // staged entries per thread in the row scan
 constexpr uint32_t kRowsPerThread = kChunkE / kThreads;  // rows of a chunk per thread
@@ -46,7 +46,7 @@ constexpr uint32_t kTable = 1u << kTableBits;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 static_assert(kWin % kThreads == 0 && kChunkE % kThreads == 0 && kThreads % kWave == 0,
               "the window and the rows split evenly over the threads");
-static_assert(kTable > kWin, "a free slot is always left");
+static_assert(kTable > kWin && kMidTable > kMid, "a free slot is always left");
 constexpr int kBigThreads = 1024;
 constexpr uint32_t kBitmapWords = 32768;          // 128 KB: 2^20 lines per pass
 constexpr uint32_t kParts = 1024;                 // parts of the rows in the reduction
