@@ -385,7 +385,26 @@ __global__ __launch_bounds__(kThreads) void k_nbr_reduce(const int32_t *__restri
     const uint32_t r1 = min(n_rows, r0 + per_part);
     double acc = 0.0;
     uint32_t cnt = 0;
-    for (uint32_t r = r0 + threadIdx.x; r < r1; r += kThreads) {
+    uint32_t r = r0 + threadIdx.x;
+    // four rows' loads in flight at a time; the sum still runs in row order
+    for (; r + 3 * kThreads < r1; r += 4 * kThreads) {
+        int32_t ps[4], pe[4];
+        uint32_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            ps[u] = rowptr[r + u * kThreads];
+            pe[u] = rowptr[r + u * kThreads + 1];
+            v[u] = nd[r + u * kThreads];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t s = clamp_ptr(ps[u], nnz), e = clamp_ptr(pe[u], nnz);
+            if (e <= s) continue;
+            acc += (double)v[u] / (double)(e - s);
+            ++cnt;
+        }
+    }
+    for (; r < r1; r += kThreads) {
         const uint32_t s = clamp_ptr(rowptr[r], nnz), e = clamp_ptr(rowptr[r + 1], nnz);
         if (e <= s) continue;
         acc += (double)nd[r] / (double)(e - s);
