@@ -14,11 +14,31 @@ def test_constant_edges():
     assert f[0] == math.log2(1 + n) and f[1] == math.log2(1 + m)
     assert math.isclose(f[2], math.log2(1 + m / n))
     assert math.isclose(f[3], math.log2(1 + n))          # every pair collides
+    assert math.isclose(f[4], math.log2(1 + n))
     assert math.isclose(f[5], math.log2(1 + n))          # one value, K times
-    assert f[7] == 1 / F.K_SPREAD
+    assert math.isclose(f[6], math.log2(1 + n))
+    assert f[7] == 1 / F.K_SPREAD and f[8] == 1 / F.K_SPREAD
     assert f[9] == 0.0                                   # src == dst
-    assert f[10] == 1 / 1024                             # one cache line per window
+    assert f[10] == 1 / 1024 and f[11] == 1 / 1024       # one cache line per window
     assert f[12] == 1.0 and f[14] == 1.0                 # all neighbours equal
+    assert f[13] == 1.0 and f[15] == 1.0
+
+
+def test_constant_destination_distinct_sources():
+    # dst constant, src = e: only the destination side is concentrated, so
+    # every dst-side feature takes its all-equal value and every src-side one
+    # its all-distinct value (this separates f[6] from f[5])
+    m = 64 * 1024
+    n = m
+    src = np.arange(m, dtype=np.int64)
+    dst = np.full(m, 7, np.int64)
+    f = F.features(src, dst, n)
+    assert math.isclose(f[6], math.log2(1 + n))          # maxcount_dst = K
+    assert math.isclose(f[5], math.log2(1 + n / F.K_SPREAD))  # maxcount_src = 1
+    assert math.isclose(f[4], math.log2(1 + n)) and f[3] == 0.0
+    assert f[8] == 1 / F.K_SPREAD and f[7] == 1.0
+    assert f[13] == 1.0 and f[12] == 0.0
+    assert f[11] == 1 / 1024 and math.isclose(f[10], 32 / 1024)
 
 
 def test_grouped_sources_aligned_windows():

@@ -338,6 +338,37 @@ def test_adam_first_step_is_signed_learning_rate():
     assert np.allclose(P, -0.01 * np.sign(grad), rtol=1e-12)
 
 
+@pytest.mark.parametrize("b1,b2", [(0.9, 0.999), (0.5, 0.75)])
+def test_adam_constant_gradient_moves_by_the_learning_rate_every_step(b1, b2):
+    # With the same gradient g at every step, m1_t = (1 - b1^t) g and
+    # m2_t = (1 - b2^t) g^2, so the bias-corrected moments are exactly g and
+    # g^2 at every t and each step moves a parameter by -lr * sign(g).  A
+    # wrong exponent in the bias correction breaks this from t = 2 on.
+    grad = np.array([0.5, -2.0, 1e-3, -7.0, 3.0])
+    P = np.zeros(5)
+    m1, m2 = np.zeros(5), np.zeros(5)
+    for t in (1, 2, 3, 4):
+        oracle.adam(P, m1, m2, grad, t, lr=0.01, b1=b1, b2=b2, eps=0.0)
+        assert np.allclose(P, -0.01 * t * np.sign(grad), rtol=1e-12, atol=0.0), t
+        assert np.allclose(m1, (1 - b1 ** t) * grad, rtol=1e-12)
+        assert np.allclose(m2, (1 - b2 ** t) * grad * grad, rtol=1e-12)
+
+
+def test_adam_second_step_after_a_zero_gradient():
+    # g_1 = 0, g_2 = g: m1 = (1 - b1) g and m2 = (1 - b2) g^2, corrected by
+    # 1 - b1^2 and 1 - b2^2, so the second step is
+    # -lr * sign(g) * sqrt(1 + b2) / (1 + b1) (and the first step is zero).
+    b1, b2, lr = 0.9, 0.999, 0.01
+    grad = np.array([0.5, -2.0, 4.0])
+    P = np.zeros(3)
+    m1, m2 = np.zeros(3), np.zeros(3)
+    oracle.adam(P, m1, m2, np.zeros(3), 1, lr=lr, b1=b1, b2=b2, eps=1e-300)
+    assert np.all(P == 0.0)
+    oracle.adam(P, m1, m2, grad, 2, lr=lr, b1=b1, b2=b2, eps=0.0)
+    expect = -lr * np.sign(grad) * math.sqrt(1 + b2) / (1 + b1)
+    assert np.allclose(P, expect, rtol=1e-12, atol=0.0)
+
+
 # -------------------------------------------------------------------- NBR
 def test_nbr_closed_forms():
     # vertex 0: 4 neighbours in one 32-ID line -> 1/4; vertex 1: 3 in 3 lines -> 1
