@@ -54,26 +54,57 @@ def radix_passes(n):
     return max(1, (bits + 7) // 8)
 
 
+def call_alg_bytes(call, n, m):
+    """Algorithmic bytes of one library call: what the method itself must move
+    (int32 / float32 = 4 bytes), whatever passes the implementation makes.
+    The reorder reads I and J once, writes and reads r once and writes perm
+    and order (Sec. 4.4: reads linear in m, writes linear in n); the fused
+    reorder + relabel additionally writes I' and J' (perm is then on chip);
+    the conversion reads row, col, val and writes col, val and rowptr; SpMV
+    reads col, val, rowptr and x once and writes y."""
+    return {
+        "boba_reorder": 8 * m + 16 * n,
+        "boba_reorder_relabel": 16 * m + 16 * n,
+        "boba_relabel": 16 * m + 4 * n,
+        "coo_to_csr": 20 * m + 4 * (n + 1),
+        "spmv_csr": 8 * m + 4 * (n + 1) + 8 * n,
+    }[call]
+
+
 def kernel_alg_bytes(name, n, m):
-    """Algorithmic bytes per launch: what the kernel must read and write at
-    minimum given its inputs and outputs (int32 / float32 = 4 bytes)."""
+    """The algorithmic bytes (call_alg_bytes) charged to one launch of a
+    kernel: the method's reads and writes that this kernel performs.
+    Intermediate traffic of this design (records, radix passes, bitmaps) is
+    never charged.  The conversion's bytes are spread evenly over its radix
+    scatter passes, which each move every edge once."""
     table = {
-        "scatter_min": 8 * m + 4 * n,          # read src, dst; write r once
-        "relabel": 16 * m + 4 * n,             # read src, dst, perm once; write both
-        # read key, col, val; write them (the last pass writes no keys):
-        # the mean over the ceil(bits(n - 1) / 8) passes
-        "radix_scatter": (24 * m * (radix_passes(n) - 1) + 20 * m) // radix_passes(n),
-        "spmv": 8 * m + 4 * (n + 1) + 8 * n,   # val, col, rowptr, x once, y
+        "bucket_split": 8 * m,                 # reads I and J
+        "scatter_min": 8 * m + 4 * n,          # direct path: reads I and J, writes r
+        "bucket_min": 4 * n,                   # writes r
+        "rank_count": 4 * n,                   # reads r
+        "rank_block": 4 * n,                   # writes order
+        "rank_perm": 4 * n,                    # writes perm
+        "bucket_relabel": 4 * n,               # reads perm
+        "tile_unsplit": 8 * m,                 # writes I' and J'
+        "relabel": 16 * m + 4 * n,             # the whole standalone relabel
+        "radix_scatter": call_alg_bytes("coo_to_csr", n, m) // radix_passes(n),
+        "spmv": call_alg_bytes("spmv_csr", n, m),
+    }
+    return table.get(name)
+
+
+def kernel_impl_bytes(name, n, m):
+    """This design's own traffic per launch (records, radix passes): what a
+    kernel reads and writes as implemented, for comparison with the counters.
+    Not the roofline's bytes."""
+    table = {
         "bucket_split": 16 * m,                # read src, dst; write one record each
         "bucket_min": 8 * m + 4 * n,           # read the records; write r
         "bucket_relabel": 16 * m + 4 * n,      # read the records, perm; write new IDs
         "tile_unsplit": 24 * m,                # read records and new IDs; write src', dst'
-        "rank": 12 * n,                        # read r, write perm, order
-        "mark": 4 * n,                         # read r (bitmap writes are ours)
-        "rank_count": 4 * n,                   # read r
-        "rank_scatter": 12 * n,                # read r; write {r, v} per occurring vertex (<= n)
-        "rank_block": 16 * n,                  # read the entries; write ranks and order
-        "rank_perm": 16 * n,                   # read entries and ranks; write perm
+        "radix_scatter": (24 * m * (radix_passes(n) - 1) + 20 * m) // radix_passes(n),
+        "spmv": 8 * m + 4 * (n + 1) + 8 * n,
+        "relabel": 16 * m + 4 * n,
     }
     return table.get(name)
 
@@ -183,6 +214,9 @@ def main():
     ap.add_argument("--cold", action="store_true",
                     help="also time boba_reorder cold (after a 512 MiB write that flushes L2 and the Infinity "
                          "Cache); on by default for graphs of at most 2^24 edges")
+    ap.add_argument("--pagerank", type=int, default=1, help="time 20 PageRank iterations before and after (0: skip)")
+    ap.add_argument("--selector-graphs", type=int, default=100,
+                    help="held-out graphs for the selector leg (0: skip)")
     ap.add_argument("--calibrate", action="store_true",
                     help="run a plain elementwise kernel over 256 MiB (reads and writes 256 MiB) first, "
                          "to scale hardware byte counters")
@@ -214,6 +248,10 @@ def main():
         batch = graphgen.make_batch(specs, workers=min(16, os.cpu_count() or 1))
         log(f"batch of {args.batch_graphs} graphs, m={int(batch[0][-1])} n={int(batch[1][-1])}, "
             f"generated in {time.perf_counter() - t0:.1f}s")
+
+    sel_data = None
+    if args.selector_graphs > 0:
+        sel_data = prepare_selector_graphs(args.selector_graphs)
 
     import torch
     from paper_2306_10410_amd import boba
@@ -252,8 +290,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    stage_names = ["reorder_relabel", "coo_to_csr", "spmv"]
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    K = args.steps
     ws_rr = torch.empty(boba.boba_reorder_relabel_workspace(n, m), dtype=torch.uint8, device=dev)
 
     def step(e=None):
@@ -269,9 +306,12 @@ def main():
         if e:
             e[3].record()
 
+    def reorder_call():
+        boba.boba_reorder(src, dst, n, ws=ws_r, perm=perm, order=order)
+
     # x in the new labelling (x2[perm[v]] = x[v], on the host), so the
     # reordered product equals the original one
-    boba.boba_reorder(src, dst, n, ws=ws_r, perm=perm, order=order)
+    reorder_call()
     x2_h = np.empty(n, np.float32)
     x2_h[perm.cpu().numpy()] = g.x
     x2.copy_(torch.from_numpy(x2_h))
@@ -281,123 +321,117 @@ def main():
     torch.cuda.synchronize()
     assert boba.boba_check_device_error() == boba.BOBA_OK
 
-    boba.boba_timing_enable(True)
-    boba.boba_timing_collect()
-    log(f"timing {args.steps} steps")
+    # --- timed region: exactly K steps, library timing off (no per-kernel
+    # events), torch events between the three calls of each step
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
+    stage_names = ["reorder_relabel", "coo_to_csr", "spmv"]
+    log(f"timing {K} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(K):
         step(ev[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kern = boba.boba_timing_collect()
-    stage_ms = {name: float(np.mean([ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(args.steps)]))
+    stage_ms = {name: float(np.mean([ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(K)]))
                 for i, name in enumerate(stage_names)}
-    ms_per_step = wall * 1e3 / args.steps
+    ms_per_step = wall * 1e3 / K
     log(f"{ms_per_step:.3f} ms/step; stages {stage_ms}")
 
-    # the reorder alone (the metric's edges/s): boba_reorder timed the same number of times
-    er = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
-    for k in range(args.steps):
-        er[k][0].record()
-        boba.boba_reorder(src, dst, n, ws=ws_r, perm=perm, order=order)
-        er[k][1].record()
-    torch.cuda.synchronize()
-    reorder_kern = boba.boba_timing_collect()
-    boba.boba_timing_enable(False)
-    stage_ms["reorder"] = float(np.mean([er[k][0].elapsed_time(er[k][1]) for k in range(args.steps)]))
+    # Every other time below is taken the same way: `reps` calls back to back
+    # on the stream, an event between consecutive calls, library timing off;
+    # the mean of the per-call intervals.
+    def timed_calls(fn, reps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        e[0].record()
+        for k in range(reps):
+            fn()
+            e[k + 1].record()
+        torch.cuda.synchronize()
+        return float(np.mean([e[k].elapsed_time(e[k + 1]) for k in range(reps)]))
+
+    # the reorder alone: the metric's edges/s
+    reorder_ms = timed_calls(reorder_call, K)
+    log(f"boba_reorder alone: {reorder_ms:.3f} ms")
+
+    # SpMV and CSR build on the input labelling ("before") and on the BOBA
+    # labelling ("after"), each call timed alone, both legs the same way
+    log("before/after legs")
+    rp0 = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    col0 = torch.empty(m, dtype=torch.int32, device=dev)
+    val0 = torch.empty(m, dtype=torch.float32, device=dev)
+    y0 = torch.empty(n, dtype=torch.float32, device=dev)
+    legs = {}
+    for name, (a, b, xx, out_csr, yy) in (("before", (src, dst, x, (rp0, col0, val0), y0)),
+                                         ("after", (s2, d2, x2, (rowptr, col, val_c), y))):
+        reps = max(args.before_reps, 1)
+        csr_ms = timed_calls(lambda: boba.coo_to_csr(a, b, val, n, ws=ws_c, out=out_csr), reps)
+        spmv_ms = timed_calls(lambda: boba.spmv_csr(out_csr[0], out_csr[1], out_csr[2], xx, y=yy, ws=ws_s), reps)
+        legs[name] = {"coo_to_csr_ms": csr_ms, "spmv_ms": spmv_ms, "spmv_gflops": 2 * m / (spmv_ms * 1e-3) / 1e9}
+    log(f"legs {legs}")
+    # the reordered SpMV must reproduce the input-order one
+    yb = y0.cpu().numpy().astype(np.float64)
+    ya = y.cpu().numpy().astype(np.float64)[perm.cpu().numpy()]
+    spmv_agree = float(np.linalg.norm(ya - yb) / max(np.linalg.norm(yb), 1e-30))
+    assert boba.boba_check_device_error() == boba.BOBA_OK
+
     cold_ms = None
     if args.cold or m <= (1 << 24):
         flush = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
         ct = []
-        for _ in range(args.steps):
+        for _ in range(K):
             flush.fill_(1)
             e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
             e[0].record()
-            boba.boba_reorder(src, dst, n, ws=ws_r, perm=perm, order=order)
+            reorder_call()
             e[1].record()
             torch.cuda.synchronize()
             ct.append(e[0].elapsed_time(e[1]))
         cold_ms = float(np.median(ct))
         del flush
         log(f"boba_reorder cold: {cold_ms:.3f} ms")
+
+    # --- instrumented pass (separate from every figure above): the library
+    # brackets each of its kernels with HIP events on its launch stream, over
+    # K more steps and K more reorders; per-kernel durations for the roofline
+    boba.boba_timing_enable(True)
+    boba.boba_timing_collect()
+    for _ in range(K):
+        step()
+    torch.cuda.synchronize()
+    kern = boba.boba_timing_collect()
+    for _ in range(K):
+        reorder_call()
+    torch.cuda.synchronize()
+    reorder_kern = boba.boba_timing_collect()
+    boba.boba_timing_enable(False)
+
     # a plain device-to-device copy of 1 GiB: the bandwidth a streaming kernel can expect here
     cp_a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
     cp_b = torch.empty_like(cp_a)
     cp_b.copy_(cp_a)
-    cpt = []
-    for _ in range(5):
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-        e[0].record()
-        cp_b.copy_(cp_a)
-        e[1].record()
-        torch.cuda.synchronize()
-        cpt.append(e[0].elapsed_time(e[1]))
-    copy_GBs = 2 * (1 << 30) / (float(np.median(cpt)) * 1e-3) / 1e9  # read + write
+    copy_GBs = 2 * (1 << 30) / (timed_calls(lambda: cp_b.copy_(cp_a), 5) * 1e-3) / 1e9  # read + write
     del cp_a, cp_b
     log(f"device copy: {copy_GBs:.0f} GB/s")
-    log(f"boba_reorder alone: {stage_ms['reorder']:.3f} ms")
 
     # the standalone relabel with a given perm: one gather per endpoint vs the bucketed path
     s_o, d_o = torch.empty_like(src), torch.empty_like(dst)
     ws_rl = torch.empty(boba.boba_relabel_bucketed_workspace(n, m), dtype=torch.uint8, device=dev)
-    relabel_ms = {}
-    for name, fn in (("gather", lambda: boba.boba_relabel(src, dst, perm, src_out=s_o, dst_out=d_o)),
-                     ("bucketed", lambda: boba.boba_relabel_bucketed(src, dst, perm, src_out=s_o, dst_out=d_o,
-                                                                     ws=ws_rl))):
-        fn()
-        rt = []
-        for _ in range(3):
-            e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-            e[0].record()
-            fn()
-            e[1].record()
-            torch.cuda.synchronize()
-            rt.append(e[0].elapsed_time(e[1]))
-        relabel_ms[name] = float(np.median(rt))
+    relabel_ms = {
+        "gather": timed_calls(lambda: boba.boba_relabel(src, dst, perm, src_out=s_o, dst_out=d_o), 3),
+        "bucketed": timed_calls(lambda: boba.boba_relabel_bucketed(src, dst, perm, src_out=s_o, dst_out=d_o,
+                                                                   ws=ws_rl), 3)}
     del s_o, d_o, ws_rl
     log(f"standalone relabel: gather {relabel_ms['gather']:.3f} ms, bucketed {relabel_ms['bucketed']:.3f} ms")
 
     # the non-atomic scatter of the paper's GPU kernel (Sec. 4.4): what the
     # exact minimum costs here, and how much of the order the race changes
     perm_r, order_r = torch.empty_like(perm), torch.empty_like(order)
-    boba.boba_reorder(src, dst, n, ws=ws_r, perm=perm_r, order=order_r, flags=boba.BOBA_FLAG_RACY)
-    racy_t = []
-    for _ in range(args.steps):
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-        e[0].record()
-        boba.boba_reorder(src, dst, n, ws=ws_r, perm=perm_r, order=order_r, flags=boba.BOBA_FLAG_RACY)
-        e[1].record()
-        torch.cuda.synchronize()
-        racy_t.append(e[0].elapsed_time(e[1]))
-    racy = {"reorder_ms": float(np.mean(racy_t)), "exact_reorder_ms": stage_ms["reorder"],
+    racy_ms = timed_calls(lambda: boba.boba_reorder(src, dst, n, ws=ws_r, perm=perm_r, order=order_r,
+                                                    flags=boba.BOBA_FLAG_RACY), K)
+    racy = {"reorder_ms": racy_ms, "exact_reorder_ms": reorder_ms,
             "same_new_id_fraction": float((perm_r == perm).float().mean())}
     del order_r
     log(f"racy scatter: {racy['reorder_ms']:.3f} ms, {racy['same_new_id_fraction']:.4f} of the IDs as exact")
-
-    # SpMV and CSR build on the input labelling ("before")
-    log("before-reorder leg")
-    rp0 = torch.empty(n + 1, dtype=torch.int32, device=dev)
-    col0 = torch.empty(m, dtype=torch.int32, device=dev)
-    val0 = torch.empty(m, dtype=torch.float32, device=dev)
-    y0 = torch.empty(n, dtype=torch.float32, device=dev)
-    b_csr, b_spmv = [], []
-    for _ in range(args.before_reps):
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-        e[0].record()
-        boba.coo_to_csr(src, dst, val, n, ws=ws_c, out=(rp0, col0, val0))
-        e[1].record()
-        boba.spmv_csr(rp0, col0, val0, x, y=y0, ws=ws_s)
-        e[2].record()
-        torch.cuda.synchronize()
-        b_csr.append(e[0].elapsed_time(e[1]))
-        b_spmv.append(e[1].elapsed_time(e[2]))
-    before_csr_ms, before_spmv_ms = float(np.median(b_csr)), float(np.median(b_spmv))
-    # the reordered SpMV must reproduce the input-order one
-    yb = y0.cpu().numpy().astype(np.float64)
-    ya = y.cpu().numpy().astype(np.float64)[perm.cpu().numpy()]
-    spmv_agree = float(np.linalg.norm(ya - yb) / max(np.linalg.norm(yb), 1e-30))
-    assert boba.boba_check_device_error() == boba.BOBA_OK
 
     # locality of the CSR rows (NBR of Sec. 5.2, 32-ID lines) before and after
     ws_nbr = torch.empty(boba.boba_nbr_workspace(n, m), dtype=torch.uint8, device=dev)
@@ -406,15 +440,8 @@ def main():
     boba.coo_to_csr(sr, dr, val, n, ws=ws_c, out=(rp0, col0, val0))
     del sr, dr, perm_r
     racy["nbr_over_nonempty_rows"] = boba.boba_nbr(rp0, col0, n, 32, ws=ws_nbr)[1]
-    rt = []
-    for _ in range(args.before_reps):
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-        e[0].record()
-        boba.spmv_csr(rp0, col0, val0, x2, y=y0, ws=ws_s)
-        e[1].record()
-        torch.cuda.synchronize()
-        rt.append(e[0].elapsed_time(e[1]))
-    racy["spmv_gflops"] = 2 * m / (float(np.median(rt)) * 1e-3) / 1e9
+    racy_spmv_ms = timed_calls(lambda: boba.spmv_csr(rp0, col0, val0, x2, y=y0, ws=ws_s), max(args.before_reps, 1))
+    racy["spmv_gflops"] = 2 * m / (racy_spmv_ms * 1e-3) / 1e9
     log(f"racy order: NBR {racy['nbr_over_nonempty_rows']:.4f}, SpMV {racy['spmv_gflops']:.1f} GFLOP/s")
     # the before-leg CSR again, for NBR before
     boba.coo_to_csr(src, dst, val, n, ws=ws_c, out=(rp0, col0, val0))
@@ -431,37 +458,57 @@ def main():
     del ws_nbr
     assert boba.boba_check_device_error() == boba.BOBA_OK
 
-    pagerank = bench_pagerank(src, dst, s2, d2, perm, n, m, dev, ws_c)
-    log(f"PageRank x{pagerank['iters']}: {pagerank['ms_before']:.2f} -> {pagerank['ms_after']:.2f} ms")
+    pagerank = bench_pagerank(src, dst, s2, d2, perm, n, m, dev, ws_c) if args.pagerank else None
+    if pagerank:
+        log(f"PageRank x{pagerank['iters']}: {pagerank['ms_before']:.2f} -> {pagerank['ms_after']:.2f} ms")
 
     binned = None
     if args.bin_bits > 0:
-        binned = bench_binned(args, g, src, dst, val, x, dev, ws_rr, ws_c, ws_s, before_spmv_ms)
+        binned = bench_binned(args, g, src, dst, val, x, dev, ws_rr, ws_c, ws_s, legs["before"]["spmv_ms"])
 
     kernels = {}
     for name, (tot, cnt) in list(kern.items()) + [(f"{k} [boba_reorder alone]", v) for k, v in reorder_kern.items()]:
-        per_step = cnt / args.steps
+        per_step = cnt / K
         avg = tot / cnt
-        entry = {"avg_ms": avg, "launches_per_step": per_step, "ms_per_step": tot / args.steps}
-        ab = kernel_alg_bytes(name.split(" [")[0], n, m)
+        entry = {"avg_ms": avg, "launches_per_step": per_step, "ms_per_step": tot / K}
+        base = name.split(" [")[0]
+        ab = kernel_alg_bytes(base, n, m)
         if ab is not None:
             entry["alg_bytes_per_launch"] = ab
             entry["achieved_GBs"] = ab / (avg * 1e-3) / 1e9
             entry["hbm_frac"] = entry["achieved_GBs"] / HBM_PEAK_GBS
+        ib = kernel_impl_bytes(base, n, m)
+        if ib is not None:
+            entry["impl_bytes_per_launch"] = ib
+        tr = pmc_traffic(base, args.workload, per_step) if "[" not in name else None
+        if tr is not None:
+            entry["traffic_bytes_per_launch"] = tr
         kernels[name] = entry
-    dom = max((k for k in kernels if "alg_bytes_per_launch" in kernels[k] and "[" not in k),
-              key=lambda k: kernels[k]["ms_per_step"])
+    # the roofline object: the kernel that takes the most time per step
+    dom = max((k for k in kernels if "[" not in k), key=lambda k: kernels[k]["ms_per_step"])
     dk = kernels[dom]
-    traffic = pmc_traffic(dom, args.workload, dk["launches_per_step"])
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["achieved_GBs"], "peak": HBM_PEAK_GBS,
-                "frac_of_measured_copy": dk["achieved_GBs"] / copy_GBs,
-                "unit": "GB/s", "frac": dk["achieved_GBs"] / HBM_PEAK_GBS, "traffic": traffic,
-                "alg_bytes_per_launch": dk["alg_bytes_per_launch"], "avg_ms": dk["avg_ms"]}
+    alg = dk.get("alg_bytes_per_launch", 0)
+    traffic = dk.get("traffic_bytes_per_launch")
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": alg / (dk["avg_ms"] * 1e-3) / 1e9,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg / (dk["avg_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "traffic": traffic, "traffic_over_alg_bytes": (traffic / alg) if (traffic and alg) else None,
+                "alg_bytes_per_launch": alg, "avg_ms": dk["avg_ms"],
+                "frac_of_measured_copy": alg / (dk["avg_ms"] * 1e-3) / 1e9 / copy_GBs,
+                "bytes": "algorithmic: the method's own reads and writes charged to this kernel "
+                         "(call bytes spread over the call's radix passes for the conversion)"}
+
+    # each call of the path against its own algorithmic bytes (uninstrumented times)
+    call_ms = {"boba_reorder": reorder_ms, "boba_reorder_relabel": stage_ms["reorder_relabel"],
+               "coo_to_csr": stage_ms["coo_to_csr"], "spmv_csr": stage_ms["spmv"]}
+    calls = {}
+    for c, t in call_ms.items():
+        b = call_alg_bytes(c, n, m)
+        calls[c] = {"ms": t, "alg_bytes": b, "achieved_GBs": b / (t * 1e-3) / 1e9,
+                    "hbm_frac": b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
     batched = bench_batch(batch, args.batch_reps, dev) if batch is not None else None
+    selector_leg = bench_selector(sel_data) if sel_data is not None else None
 
-    reorder_ms = stage_ms["reorder"]
-    reorder_alg = 8 * m + 16 * n  # read I, J; write and read r; write perm and order
     cpu = None
     if args.cpu_budget > 0:
         log("CPU oracle baseline")
@@ -472,7 +519,7 @@ def main():
         "value": m / (reorder_ms * 1e-3),
         "unit": "edges/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": K,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
         "higher_is_better": True,
@@ -483,17 +530,20 @@ def main():
         "config": {"workload": args.workload, "n": n, "m": m,
                    "generator": _describe(args.workload),
                    "step": "boba_reorder_relabel -> coo_to_csr -> spmv_csr",
-                   "value": "m / duration of boba_reorder alone (mean of --steps calls, HIP events)"},
+                   "value": "m / duration of boba_reorder alone (mean of --steps back-to-back calls, HIP events, "
+                            "no per-kernel events)"},
         "reorder_ms": reorder_ms,
-        "reorder_hbm_frac_alg": reorder_alg / (reorder_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "reorder_hbm_frac_alg": calls["boba_reorder"]["hbm_frac"],
         "path_edges_per_s": m / (ms_per_step * 1e-3),
         "stages_ms": stage_ms,
-        "spmv_gflops_before": 2 * m / (before_spmv_ms * 1e-3) / 1e9,
-        "spmv_gflops_after": 2 * m / (stage_ms["spmv"] * 1e-3) / 1e9,
-        "spmv_speedup_after_reorder": before_spmv_ms / stage_ms["spmv"],
+        "calls": calls,
+        "spmv_gflops_before": legs["before"]["spmv_gflops"],
+        "spmv_gflops_after": legs["after"]["spmv_gflops"],
+        "spmv_speedup_after_reorder": legs["before"]["spmv_ms"] / legs["after"]["spmv_ms"],
         "spmv_dtype": "f32",
-        "coo_to_csr_ms_before": before_csr_ms,
-        "coo_to_csr_ms_after": stage_ms["coo_to_csr"],
+        "coo_to_csr_ms_before": legs["before"]["coo_to_csr_ms"],
+        "coo_to_csr_ms_after": legs["after"]["coo_to_csr_ms"],
+        "legs": legs,
         "spmv_reordered_vs_input_rel_l2": spmv_agree,
         "kernels": kernels,
         "roofline": roofline,
@@ -501,6 +551,7 @@ def main():
         "reorder_ms_cold": cold_ms,
         "cpu_baseline": cpu,
         "batched": batched,
+        "selector": selector_leg,
         "binned": binned,
         "nbr": nbr,
         "pagerank": pagerank,
@@ -670,6 +721,69 @@ def bench_batch(batch, reps, dev):
             "graphs": G, "m": m_tot, "n": int(vo[-1]), "batched_ms": batched_ms, "per_graph_ms": per_graph_ms,
             "speedup": per_graph_ms / batched_ms, "edges_per_s": m_tot / (batched_ms * 1e-3),
             "identical_to_per_graph": same, "plan": info, "tuning": best, "includes": "reorder + relabel"}
+
+
+def prepare_selector_graphs(count):
+    """The first graphs of the selector's held-out set (the same 10:1 mix of
+    regular and large graphs), generated by forked workers before the GPU is
+    touched."""
+    from paper_2306_10410_amd import selector
+    n_large = max(1, count // 11)
+    n_reg = count - n_large
+    specs = selector.heldout_specs(500, 50)
+    specs = specs[:n_reg] + specs[500:500 + n_large]
+    t0 = time.perf_counter()
+    pool = selector.start_pool(min(16, os.cpu_count() or 1))
+    graphs = list(pool.map(selector._gen, specs, chunksize=2))
+    pool.shutdown()
+    log(f"selector leg: {len(specs)} held-out graphs generated in {time.perf_counter() - t0:.1f}s")
+    return specs, graphs
+
+
+def bench_selector(sel_data):
+    """The shipped selector on held-out graphs: its total time (features and
+    inference included) against the oracle choice (the faster of the two
+    measured paths per graph), the gate alone, the network alone, always
+    reordering (the method without the selector) and never reordering."""
+    import numpy as np
+    import torch
+
+    from paper_2306_10410_amd import boba, graphgen, selector
+
+    specs, graphs = sel_data
+    model = selector.load_model(selector.DEFAULT_MODEL)
+    if model is None:
+        return {"error": "no valid shipped model"}
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    selector.warm_up(None, seconds=1.0)
+    ws_f = torch.empty(boba.load().boba_graph_features_workspace(), dtype=torch.uint8, device=dev)
+    X = np.zeros((len(specs), selector.N_FEAT), np.float32)
+    rows = []
+    for i, (sp, (src_h, dst_h)) in enumerate(zip(specs, graphs)):
+        src = torch.from_numpy(src_h).to(dev)
+        dst = torch.from_numpy(dst_h).to(dev)
+        val = torch.from_numpy(graphgen.uniform_values(src_h.size, sp.seed + 3)).to(dev)
+        x = torch.from_numpy(graphgen.uniform_values(sp.n, sp.seed + 4)).to(dev)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record()
+        f = boba.boba_graph_features(src, dst, sp.n, ws=ws_f)
+        e[1].record()
+        torch.cuda.synchronize()
+        X[i] = f.cpu().numpy()
+        med = selector.measure_paths(src, dst, val, x, sp.n, reps=3)
+        med["t_feat"] = e[0].elapsed_time(e[1])
+        med.update({"kind": sp.kind, "n": sp.n, "m": int(src_h.size)})
+        rows.append(med)
+    t_inf = selector.time_inference(model.params)
+    res = selector.evaluate(model.params, X, rows, t_inf, model.gate)
+    res.update({"t_infer_ms": t_inf, "seconds": time.perf_counter() - t0,
+                "graphs_desc": "the first held-out graphs of the selector's training run (regular and large, "
+                               "10:1), each path the median of 3 timings after a warm-up round"})
+    log(f"selector: {res['selector_vs_oracle']:.3f} of the oracle choice (gate only "
+        f"{res['gate_only_vs_oracle']:.3f}, network only {res['ungated_selector_vs_oracle']:.3f}, "
+        f"never {res['never_vs_oracle']:.3f}, always {res['always_vs_oracle']:.3f}) in {res['seconds']:.1f}s")
+    return res
 
 
 def _describe(workload):

@@ -45,6 +45,7 @@ typedef int32_t boba_status;
 #define BOBA_ERR_OVERFLOW 3  /* m or n >= 2^31, or 2m + n >= 2^32 */
 #define BOBA_ERR_WORKSPACE 4 /* workspace null or smaller than the query said */
 #define BOBA_ERR_HIP 5       /* a HIP runtime call or kernel launch failed */
+#define BOBA_ERR_TIMEOUT 6   /* a batched plan's bounded wait gave up (device-detected) */
 
 /* boba_reorder flags */
 #define BOBA_FLAG_INTERLEAVED 0x1u /* flatten as I(0) J(0) I(1) J(1) ... (Fig. 1)
@@ -60,9 +61,11 @@ typedef int32_t boba_status;
  * thread ("" if none).  The string stays valid until the next call. */
 BOBA_API const char *boba_last_error(void);
 
-/* Waits for `stream`, then reports whether any kernel on the current device saw
- * a vertex ID out of range since the last check (*code = BOBA_ERR_RANGE) or not
- * (*code = BOBA_OK), and clears the flag.  `code` is a host pointer. */
+/* Waits for `stream`, then reports what the kernels on the current device
+ * flagged since the last check, and clears it: *code = BOBA_ERR_TIMEOUT if a
+ * batched plan's wait for another workgroup gave up (that launch's outputs
+ * are then unspecified), else BOBA_ERR_RANGE if a vertex ID was out of range,
+ * else BOBA_OK.  `code` is a host pointer. */
 BOBA_API boba_status boba_check_device_error(hipStream_t stream, int32_t *code);
 
 /* ------------------------------------------------------------- reorder ---
@@ -184,6 +187,12 @@ typedef struct boba_tuning {
     int32_t scatter_tile; /* positions per scatter item of a large graph (default 262144) */
     int32_t vertex_tile;  /* vertices per mark / rank item (default 65536) */
     int32_t relabel_tile; /* edges per relabel item (default 262144) */
+    int32_t queues;       /* 1..8 ticket queues the graphs are dealt to (default 8, one per
+                             XCD); with fewer, the workgroups of the other XCDs run the
+                             items by helping.  Never changes results. */
+    int32_t spin_limit;   /* sleeps before a wait for another workgroup gives up
+                             (default 2^22, about 0.4 s); a give-up is reported as
+                             BOBA_ERR_TIMEOUT by boba_check_device_error */
 } boba_tuning;
 typedef struct boba_batch_plan boba_batch_plan;
 BOBA_API size_t boba_batch_workspace(int32_t G, const int64_t *h_edge_off, const int64_t *h_vert_off,
@@ -261,11 +270,12 @@ BOBA_API boba_status boba_pagerank(const int32_t *rowptr, const int32_t *col, co
  *   line_ids       a power of two in [1, 2^30] (32: 128-byte lines of 4-byte values).
  *   lines_per_row  int32[n_rows] output, distinct lines per row (0 for empty
  *                  rows), or NULL.
- *   result         device double[2] output: result[0] = sum of the ratios over
- *                  the non-empty rows, result[1] = how many rows that is, so
- *                  NBR over all rows = result[0] / n_rows and over non-empty
- *                  rows = result[0] / result[1].  The sum is taken in a fixed
- *                  order (bit-reproducible).
+ *   result         device double[4] output: result[0] = sum of the ratios over
+ *                  the non-empty rows, result[1] = how many rows that is,
+ *                  result[2] = NBR over all rows (result[0] / n_rows, 0 when
+ *                  n_rows = 0), result[3] = NBR over the non-empty rows
+ *                  (result[0] / result[1], 0 when there are none).  The sum
+ *                  is taken in a fixed order (bit-reproducible).
  *   ws             at least boba_nbr_workspace(n_rows, nnz) bytes, 256-byte aligned.
  * Column IDs outside [0, n_cols) are flagged (boba_check_device_error); the
  * counts of the rows holding them are then unspecified (never an access out

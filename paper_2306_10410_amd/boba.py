@@ -16,10 +16,11 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libboba.so")
 
-BOBA_OK, BOBA_ERR_ARG, BOBA_ERR_RANGE, BOBA_ERR_OVERFLOW, BOBA_ERR_WORKSPACE, BOBA_ERR_HIP = range(6)
+BOBA_OK, BOBA_ERR_ARG, BOBA_ERR_RANGE, BOBA_ERR_OVERFLOW, BOBA_ERR_WORKSPACE, BOBA_ERR_HIP, BOBA_ERR_TIMEOUT = range(7)
 BOBA_FLAG_INTERLEAVED = 0x1
 BOBA_FLAG_RACY = 0x2  # non-atomic scatter (Sec. 4.4): a valid, not unique, result
-_STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_RANGE", 3: "ERR_OVERFLOW", 4: "ERR_WORKSPACE", 5: "ERR_HIP"}
+_STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_RANGE", 3: "ERR_OVERFLOW", 4: "ERR_WORKSPACE", 5: "ERR_HIP",
+           6: "ERR_TIMEOUT"}
 
 # name -> (restype, argtypes); the exact C prototypes of include/boba.h
 _P, _I64, _U32, _I32, _SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_size_t
@@ -286,14 +287,13 @@ def boba_nbr(rowptr, col, n_cols: int, line_ids: int = 32, *, per_row=False, ws=
     n_rows = rowptr.numel() - 1
     dev = rowptr.device
     lines = torch.empty(max(n_rows, 0), dtype=torch.int32, device=dev) if per_row else None
-    result = torch.empty(2, dtype=torch.float64, device=dev)
+    result = torch.empty(4, dtype=torch.float64, device=dev)
     ws = _workspace(boba_nbr_workspace(n_rows, col.numel()), dev, ws)
     _check(load().boba_nbr(_ptr(rowptr), _ptr(col), n_rows, n_cols, col.numel(), line_ids, _ptr(lines),
                            _ptr(result), _ptr(ws), ws.numel(), _stream(stream)))
     if stream is not None:
         stream.synchronize()
-    total, counted = result.tolist()
-    means = (total / n_rows if n_rows else 0.0, total / counted if counted else 0.0)
+    means = tuple(result[2:].tolist())  # computed by the library's final kernel
     return (*means, lines) if per_row else means
 
 
@@ -320,7 +320,8 @@ def boba_timing_collect(max_entries: int = 64):
 class boba_tuning(ctypes.Structure):
     """Mirror of struct boba_tuning (0 = library default)."""
     _fields_ = [("small_max_n", ctypes.c_int32), ("scatter_tile", ctypes.c_int32),
-                ("vertex_tile", ctypes.c_int32), ("relabel_tile", ctypes.c_int32)]
+                ("vertex_tile", ctypes.c_int32), ("relabel_tile", ctypes.c_int32),
+                ("queues", ctypes.c_int32), ("spin_limit", ctypes.c_int32)]
 
 
 def _host_i64(a):

@@ -36,7 +36,7 @@ namespace {
 
 constexpr int kThreads = 1024;
 constexpr uint32_t kSmallMax = 32768;  // LDS capacity of the SMALL path (uint32 per vertex)
-constexpr uint32_t kSpinLimit = 1u << 22;  // about 0.4 s of sleeping
+constexpr uint32_t kSpinLimit = 1u << 22;  // default: about 0.4 s of sleeping
 constexpr uint32_t kQueues = 8;            // one per XCD: workgroup b starts on queue b % 8
 
 enum ItemType : uint32_t { ITEM_SMALL = 0, ITEM_SCATTER = 1, ITEM_MARK = 2, ITEM_SCAN = 3, ITEM_RANK = 4,
@@ -66,6 +66,7 @@ struct BatchArgs {
     uint32_t qstart[kQueues + 1];
     uint32_t *queue;      // [kQueues] ticket counters
     uint32_t *abort;      // [1] set when a wait gave up
+    uint32_t spin_limit;  // sleeps before a wait gives up
     uint32_t *done;       // [G * 6] finished items per (graph, stage)
     uint32_t *r_pool;     // large-graph r arrays
     uint2 *w_pool;        // bitmaps
@@ -104,9 +105,9 @@ __device__ void wait_stage(const BatchArgs &A, uint32_t g, uint32_t stage, uint3
         while (ld_coh(c) < need) {
             __builtin_amdgcn_s_sleep(4);
             // give up past the limit, or at once after another wait gave up
-            if (++spins > kSpinLimit || ld_coh(A.abort) != 0) {
+            if (++spins > A.spin_limit || ld_coh(A.abort) != 0) {
                 atomicOr(A.abort, 1u);
-                flag_range_error(A.flag);
+                flag_timeout(A.flag);
                 break;
             }
         }
@@ -418,6 +419,7 @@ boba_status build_host_plan(int32_t G, const int64_t *eo, const int64_t *vo, boo
     const uint32_t scatter_tile = tu && tu->scatter_tile > 0 ? (uint32_t)tu->scatter_tile : 262144u;
     const uint32_t vertex_tile = tu && tu->vertex_tile > 0 ? (uint32_t)tu->vertex_tile : 65536u;
     const uint32_t relabel_tile = tu && tu->relabel_tile > 0 ? (uint32_t)tu->relabel_tile : 262144u;
+    const uint32_t nq = tu && tu->queues > 0 ? (uint32_t)std::min<int32_t>(tu->queues, (int32_t)kQueues) : kQueues;
     H.graphs.resize(G);
     std::vector<int32_t> big, small;
     for (int32_t g = 0; g < G; ++g) {
@@ -452,7 +454,8 @@ boba_status build_host_plan(int32_t G, const int64_t *eo, const int64_t *vo, boo
     auto by_m = [&](int32_t a, int32_t b) { return H.graphs[a].m > H.graphs[b].m || (H.graphs[a].m == H.graphs[b].m && a < b); };
     std::sort(big.begin(), big.end(), by_m);
     std::sort(small.begin(), small.end(), by_m);
-    std::vector<uint64_t> load(kQueues, 0);
+    // queues past nq stay empty (their workgroups help the others)
+    std::vector<uint64_t> load(nq, 0);
     std::vector<std::vector<int32_t>> qbig(kQueues), qsmall(kQueues);
     auto deal = [&](int32_t g, std::vector<std::vector<int32_t>> &dst) {
         const size_t q = std::min_element(load.begin(), load.end()) - load.begin();
@@ -569,6 +572,7 @@ extern "C" boba_status boba_batch_plan_create(int32_t G, const int64_t *h_edge_o
     A.w_pool = L.w;
     A.p_pool = L.p;
     A.flag = flag;
+    A.spin_limit = tuning && tuning->spin_limit > 0 ? (uint32_t)tuning->spin_limit : kSpinLimit;
 
     // capture: init node + persistent kernel (one workgroup per CU)
     hipStream_t cap = nullptr;

@@ -82,6 +82,6 @@ extern "C" boba_status boba_check_device_error(hipStream_t stream, int32_t *code
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return fail(BOBA_ERR_HIP, "boba_check_device_error: %s", hipGetErrorString(e));
     }
-    *code = h ? BOBA_ERR_RANGE : BOBA_OK;
+    *code = (h & kFlagTimeout) ? BOBA_ERR_TIMEOUT : (h & kFlagRange) ? BOBA_ERR_RANGE : BOBA_OK;
     return BOBA_OK;
 }

@@ -150,8 +150,16 @@ __device__ inline uint32_t block_reduce(uint32_t x, Op op, uint32_t *lds) {
     return tot;
 }
 
+// Bits of the per-device error flag read by boba_check_device_error.
+constexpr int32_t kFlagRange = 1;    // a vertex ID out of range
+constexpr int32_t kFlagTimeout = 2;  // a bounded wait for another workgroup gave up
+
 __device__ inline void flag_range_error(int32_t *flag) {
-    if (flag) atomicOr(flag, 1);
+    if (flag) atomicOr(flag, kFlagRange);
+}
+
+__device__ inline void flag_timeout(int32_t *flag) {
+    if (flag) atomicOr(flag, kFlagTimeout);
 }
 
 }  // namespace boba

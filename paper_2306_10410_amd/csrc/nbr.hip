@@ -425,7 +425,7 @@ __global__ __launch_bounds__(kThreads) void k_nbr_reduce(const int32_t *__restri
 
 __global__ __launch_bounds__(kParts) void k_nbr_final(const double *__restrict__ part_sum,
                                                       const uint32_t *__restrict__ part_cnt, uint32_t parts,
-                                                      double *__restrict__ result) {
+                                                      uint32_t n_rows, double *__restrict__ result) {
     __shared__ double ls[kParts];
     __shared__ uint32_t lc[kParts / kWave];
     const uint32_t t = threadIdx.x;
@@ -438,8 +438,12 @@ __global__ __launch_bounds__(kParts) void k_nbr_final(const double *__restrict__
     }
     const uint32_t total = block_reduce<kParts>(c, OpSum{}, lc);
     if (t == 0) {
+        // the sum, the rows it covers, and NBR over all rows and over the
+        // non-empty rows (0 where there is no row to average over)
         result[0] = ls[0];
         result[1] = (double)total;
+        result[2] = n_rows ? ls[0] / (double)n_rows : 0.0;
+        result[3] = total ? ls[0] / (double)total : 0.0;
     }
 }
 
@@ -529,6 +533,6 @@ extern "C" boba_status boba_nbr(const int32_t *rowptr, const int32_t *col, int64
                     (const uint32_t *)nd, L.part_sum, L.part_cnt);
     }
     BOBA_LAUNCH("nbr_final", k_nbr_final, dim3(1), dim3(kParts), stream, (const double *)L.part_sum,
-                (const uint32_t *)L.part_cnt, L.parts, result);
+                (const uint32_t *)L.part_cnt, L.parts, nr, result);
     return BOBA_OK;
 }

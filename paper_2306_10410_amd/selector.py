@@ -335,17 +335,41 @@ def evaluate(params, X, rows, t_infer_ms, gate=float("-inf")):
     always = np.array([r["always"] for r in rows])
     t_sel, choose = _policy_totals(pred, rows, t_infer_ms, gate)
     t_nogate, choose_ng = _policy_totals(pred, rows, t_infer_ms, float("-inf"))
+    # the gate alone: below it keep the input order, above it always reorder
+    # (no features, no network)
+    lm = np.log2(1.0 + np.array([r["m"] for r in rows], np.float64))
+    above = lm >= gate
+    t_gate = np.where(above, always, never)
     opt = np.minimum(never, always)
     sel_total = float(t_sel.sum())
+    truth = always < never
     return {"graphs": len(rows), "gate_log2m": gate, "selector_ms": sel_total,
             "oracle_choice_ms": float(opt.sum()), "always_ms": float(always.sum()), "never_ms": float(never.sum()),
+            "gate_only_ms": float(t_gate.sum()), "mlp_only_ms": float(t_nogate.sum()),
             "selector_vs_oracle": sel_total / float(opt.sum()),
             "selector_vs_always": sel_total / float(always.sum()),
             "selector_vs_never": sel_total / float(never.sum()),
+            "gate_only_vs_oracle": float(t_gate.sum()) / float(opt.sum()),
             "ungated_selector_vs_oracle": float(t_nogate.sum()) / float(opt.sum()),
-            "decisions_reorder": int(choose.sum()), "oracle_reorder": int((always < never).sum()),
-            "agreement": float(np.mean(choose == (always < never))),
-            "mlp_agreement": float(np.mean(choose_ng == (always < never)))}
+            "never_vs_oracle": float(never.sum()) / float(opt.sum()),
+            "always_vs_oracle": float(always.sum()) / float(opt.sum()),
+            "above_gate": int(above.sum()),
+            "above_gate_oracle_reorder": int((truth & above).sum()),
+            "above_gate_selector_reorder": int((choose & above).sum()),
+            "above_gate_agreement": float(np.mean(choose[above] == truth[above])) if above.any() else None,
+            "decisions_reorder": int(choose.sum()), "oracle_reorder": int(truth.sum()),
+            "agreement": float(np.mean(choose == truth)),
+            "mlp_agreement": float(np.mean(choose_ng == truth))}
+
+
+def heldout_specs(count_regular=500, count_large=50, log2_hi=18.0, large_log2_hi=21.0):
+    """The held-out graph specs of the training run (seeds disjoint from the
+    training graphs): `count_regular` with log2 n in [10, log2_hi] and
+    `count_large` in [log2_hi, large_log2_hi]."""
+    specs = selector_specs(count_regular, graphgen.BASE_SEED + 51, log2_hi=log2_hi)
+    if count_large:
+        specs += selector_specs(count_large, graphgen.BASE_SEED + 53, log2_hi, large_log2_hi)
+    return specs
 
 
 def time_inference(params, reps=50):

@@ -20,14 +20,26 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert line["n_gpus"] == 2 and "one GPU" in line["error"]
 
 
-def test_algorithmic_bytes_table():
+def test_algorithmic_bytes_tables():
     n, m = 1 << 24, 1 << 28
-    assert bench.kernel_alg_bytes("bucket_split", n, m) == 16 * m
-    # three 8-bit passes for 24-bit row IDs; the last one writes no keys
+    # the method's bytes per call: reads of I and J linear in m, writes linear in n
+    assert bench.call_alg_bytes("boba_reorder", n, m) == 8 * m + 16 * n
+    assert bench.call_alg_bytes("coo_to_csr", n, m) == 20 * m + 4 * (n + 1)
+    assert bench.call_alg_bytes("spmv_csr", n, m) == 8 * m + 4 * (n + 1) + 8 * n
+    # charged to kernels: only the method's own reads and writes
+    assert bench.kernel_alg_bytes("bucket_split", n, m) == 8 * m
+    assert bench.kernel_alg_bytes("bucket_min", n, m) == 4 * n
+    # the conversion's bytes spread over its passes
     assert bench.radix_passes(n) == 3 and bench.radix_passes(256) == 1 and bench.radix_passes(257) == 2
-    assert bench.kernel_alg_bytes("radix_scatter", n, m) == (2 * 24 * m + 20 * m) // 3
+    assert bench.kernel_alg_bytes("radix_scatter", n, m) == (20 * m + 4 * (n + 1)) // 3
     assert bench.kernel_alg_bytes("spmv", n, m) == 8 * m + 4 * (n + 1) + 8 * n
     assert bench.kernel_alg_bytes("no_such_kernel", n, m) is None
+    # the design's own traffic stays a separate table
+    assert bench.kernel_impl_bytes("bucket_split", n, m) == 16 * m
+    assert bench.kernel_impl_bytes("radix_scatter", n, m) == (2 * 24 * m + 20 * m) // 3
+    # every kernel's charge is at most its implementation's traffic
+    for k in ("bucket_split", "bucket_min", "bucket_relabel", "tile_unsplit", "radix_scatter", "spmv", "relabel"):
+        assert bench.kernel_alg_bytes(k, n, m) <= bench.kernel_impl_bytes(k, n, m), k
 
 
 def test_pmc_traffic_requires_a_matching_source_digest(tmp_path, monkeypatch):

@@ -209,3 +209,14 @@ def test_batch_argument_errors(lib):
     assert not plan.value
     assert lib.boba_batch_plan_launch(None, None) == boba.BOBA_ERR_ARG
     assert lib.boba_batch_plan_destroy(None) == boba.BOBA_OK
+
+
+def test_status_codes_and_tuning_struct_match_the_header():
+    text = open(os.path.join(ROOT, "include", "boba.h")).read()
+    codes = {k: int(v) for k, v in re.findall(r"#define (BOBA_(?:OK|ERR_\w+)) (\d+)", text)}
+    assert codes["BOBA_ERR_TIMEOUT"] == 6
+    for k, v in codes.items():
+        assert getattr(boba, k) == v, k
+    body = re.search(r"typedef struct boba_tuning \{(.*?)\} boba_tuning;", text, re.S).group(1)
+    fields = re.findall(r"int32_t (\w+);", body)
+    assert [f for f, _ in boba.boba_tuning._fields_] == fields

@@ -94,3 +94,44 @@ def test_batched_matches_single_graph_entry_point(batch):
         p, _ = boba.boba_reorder(dev(src[a:b]), dev(dst[a:b]), n)
         assert np.array_equal(host(p), perm_b[vo[g]:vo[g + 1]])
     plan.destroy()
+
+
+def test_every_item_in_one_queue_is_run_by_all_xcds(batch):
+    # queues=1 puts every item in the first queue: the workgroups of the
+    # other XCDs run them by helping, so a graph's stages hand data from one
+    # XCD to another (the coherence the cross-workgroup handoff relies on)
+    eo, vo, src, dst = batch
+    for rep in range(2):
+        plan = boba.BatchPlan(eo, vo, dev(src), dev(dst), tuning=boba.boba_tuning(0, 65536, 16384, 65536, 1, 0))
+        plan.launch()
+        check_against_oracle(eo, vo, src, dst, host(plan.perm), host(plan.order), host(plan.src_out),
+                             host(plan.dst_out))
+        assert boba.boba_check_device_error() == boba.BOBA_OK
+        plan.destroy()
+
+
+def test_a_wait_that_gives_up_is_reported_as_a_timeout():
+    # a spin limit of one sleep: waits for other workgroups' stages give up
+    # almost at once (every kernel still runs to its end); the launch then
+    # reports BOBA_ERR_TIMEOUT, or, if no wait had to give up, exact results
+    rng = np.random.default_rng(31)
+    n, m = 1 << 18, 1 << 21
+    src = rng.integers(0, n, m, dtype=np.int32)
+    dst = rng.integers(0, n, m, dtype=np.int32)
+    eo = np.array([0, m], np.int64)
+    vo = np.array([0, n], np.int64)
+    plan = boba.BatchPlan(eo, vo, dev(src), dev(dst), tuning=boba.boba_tuning(0, 4096, 4096, 4096, 0, 1))
+    plan.launch()
+    torch.cuda.synchronize()
+    code = boba.boba_check_device_error()
+    assert code in (boba.BOBA_ERR_TIMEOUT, boba.BOBA_OK)
+    if code == boba.BOBA_OK:
+        check_against_oracle(eo, vo, src, dst, host(plan.perm), host(plan.order), host(plan.src_out),
+                             host(plan.dst_out))
+    plan.destroy()
+    # the flag was cleared: a default plan afterwards is exact and reports OK
+    plan = boba.BatchPlan(eo, vo, dev(src), dev(dst))
+    plan.launch()
+    check_against_oracle(eo, vo, src, dst, host(plan.perm), host(plan.order), host(plan.src_out), host(plan.dst_out))
+    assert boba.boba_check_device_error() == boba.BOBA_OK
+    plan.destroy()

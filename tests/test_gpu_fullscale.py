@@ -50,6 +50,34 @@ def test_rmat24_reorder_and_relabel(rmat24):
 
 
 @pytest.mark.timeout(600)
+def test_rmat24_fused_reorder_relabel_as_timed(rmat24):
+    # the call the benchmark's step times, with the same caller-owned
+    # workspace and output buffers, every element against the oracle
+    g = rmat24
+    s, d = dev(g.src), dev(g.dst)
+    ws = torch.empty(boba.boba_reorder_relabel_workspace(g.n, g.m), dtype=torch.uint8, device="cuda")
+    perm = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    order = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    s2, d2 = torch.empty_like(s), torch.empty_like(d)
+    for _ in range(2):  # a second call on the same workspace gives the same result
+        boba.boba_reorder_relabel(s, d, g.n, ws=ws, perm=perm, order=order, src_out=s2, dst_out=d2)
+    p_ref, o_ref = oracle.boba(g.src, g.dst, g.n)
+    assert np.array_equal(host(perm), p_ref)
+    assert np.array_equal(host(order), o_ref)
+    s2_ref, d2_ref = oracle.relabel(g.src, g.dst, p_ref)
+    assert np.array_equal(host(s2), s2_ref)
+    assert np.array_equal(host(d2), d2_ref)
+    assert boba.boba_check_device_error() == boba.BOBA_OK
+
+
+@pytest.mark.timeout(600)
+def test_grid4096_full_path():
+    # the mesh workload (Fig. 2's regime) through reorder, relabel, CSR and
+    # FP32 SpMV, every array against the oracle, SpMV against FP64
+    full_path_check(graphgen.make_workload("grid4096"), boba)
+
+
+@pytest.mark.timeout(600)
 def test_rmat24_destination_binning(rmat24):
     g = rmat24
     so, do = boba.boba_bin_by_dst(dev(g.src), dev(g.dst), g.n, 8)
@@ -130,6 +158,7 @@ def test_grid4096_restores_row_major_labels():
     assert np.array_equal(ph, oracle.boba(s, d, side * side)[0])
 
 
+@pytest.mark.timeout(900)
 def test_largest_bucketed_graph():
     # the bucketed path's limits: n = 2^25 vertices (1024 LDS buckets), and
     # m = 2^30 - 5 edges (2m + n < 2^32 positions, 65,536 tiles, ragged tail)
@@ -142,8 +171,10 @@ def test_largest_bucketed_graph():
     p_ref, o_ref = oracle.boba(src, dst, n)
     assert np.array_equal(host(perm), p_ref) and np.array_equal(host(order), o_ref)
     del s, d
-    # relabel on sampled edges (the whole arrays would double host memory)
-    idx = rng.integers(0, m, 1 << 22)
-    ti = torch.from_numpy(idx).cuda()
-    assert np.array_equal(host(s2[ti]), p_ref[src[idx]]) and np.array_equal(host(d2[ti]), p_ref[dst[idx]])
+    # every relabelled edge, compared in slices of 2^27 edges to bound host memory
+    step = 1 << 27
+    for k0 in range(0, m, step):
+        k1 = min(m, k0 + step)
+        assert np.array_equal(host(s2[k0:k1]), p_ref[src[k0:k1]]), k0
+        assert np.array_equal(host(d2[k0:k1]), p_ref[dst[k0:k1]]), k0
     assert boba.boba_check_device_error() == boba.BOBA_OK
