@@ -56,6 +56,12 @@ typedef int32_t boba_status;
                                       position of v, not necessarily the first,
                                       and may differ from run to run.  For
                                       measuring what the atomic costs. */
+#define BOBA_FLAG_FORCE_GENERAL 0x4u /* graphs of at most 32768 vertices and
+                                      2^21 positions (2m + n) are normally
+                                      reordered by one workgroup in one launch;
+                                      this flag sends them through the
+                                      many-workgroup path instead (identical
+                                      results).  For testing and timing. */
 
 /* Thread-local, NUL-terminated description of the most recent failure on this
  * thread ("" if none).  The string stays valid until the next call. */
@@ -82,7 +88,8 @@ BOBA_API boba_status boba_check_device_error(hipStream_t stream, int32_t *code);
  *   order     int32[n]  output, may be NULL.
  *   ws        workspace of at least boba_reorder_workspace(n, m) bytes,
  *             256-byte aligned; contents on entry are ignored.
- *   flags     0, or BOBA_FLAG_INTERLEAVED and/or BOBA_FLAG_RACY.
+ *   flags     0, or any of BOBA_FLAG_INTERLEAVED, BOBA_FLAG_RACY and
+ *             BOBA_FLAG_FORCE_GENERAL.
  * Errors: BOBA_ERR_ARG, BOBA_ERR_OVERFLOW, BOBA_ERR_WORKSPACE, BOBA_ERR_HIP. */
 BOBA_API size_t boba_reorder_workspace(int64_t n, int64_t m);
 BOBA_API boba_status boba_reorder(const int32_t *src, const int32_t *dst, int64_t m, int64_t n,

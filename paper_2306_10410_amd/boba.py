@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libboba.so")
 BOBA_OK, BOBA_ERR_ARG, BOBA_ERR_RANGE, BOBA_ERR_OVERFLOW, BOBA_ERR_WORKSPACE, BOBA_ERR_HIP, BOBA_ERR_TIMEOUT = range(7)
 BOBA_FLAG_INTERLEAVED = 0x1
 BOBA_FLAG_RACY = 0x2  # non-atomic scatter (Sec. 4.4): a valid, not unique, result
+BOBA_FLAG_FORCE_GENERAL = 0x4  # small graphs through the many-workgroup path (same results)
 _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_RANGE", 3: "ERR_OVERFLOW", 4: "ERR_WORKSPACE", 5: "ERR_HIP",
            6: "ERR_TIMEOUT"}
 

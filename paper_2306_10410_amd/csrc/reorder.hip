@@ -229,6 +229,144 @@ __global__ __launch_bounds__(kBlock) void k_relabel_scalar(const int32_t *src, c
 }
 
 
+// ------------------------------------------------- small graphs, one launch
+// A graph of at most kSmallN vertices and kSmallPositions positions is
+// reordered (and, if asked, relabelled) by one workgroup in one launch:
+// first positions by LDS atomic min over S, every vertex's key (its first
+// position, or 2m + v when it never occurs) marked in a position bitmap in the
+// workspace (small enough to stay in L2), prefix popcounts of the bitmap words
+// by the workgroup, ranks, and the relabel by LDS gathers of the ranks.  The
+// many-kernel path spends most of its time between launches at these sizes.
+constexpr int kSmallThreads = 1024;
+constexpr uint32_t kSmallN = 32768;              // r in LDS: 128 KB
+constexpr uint64_t kSmallPositions = 1ull << 21; // 2m + n: at most 8 MB of edges
+constexpr int kSmallU = 8;                       // loads in flight per thread and array
+constexpr int kSmallScanPer = 4;                 // bitmap words per thread per scan round
+
+inline bool small_graph(int64_t n, int64_t m) {
+    return n <= kSmallN && 2 * (uint64_t)m + (uint64_t)n <= kSmallPositions;
+}
+
+// Coherent loads of the bitmap (other threads wrote it through L2).
+__device__ __forceinline__ uint32_t ld_l2(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint2 ld_l2_2(const uint2 *p) {
+    const uint64_t v = __hip_atomic_load((const uint64_t *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+}
+
+template <bool INTERLEAVED, bool RACY>
+__global__ __launch_bounds__(kSmallThreads) void k_small_reorder(const int32_t *src, const int32_t *dst, uint32_t m,
+                                                                  uint32_t n, uint2 *__restrict__ W, uint32_t nw,
+                                                                  int32_t *__restrict__ perm,
+                                                                  int32_t *__restrict__ order, int32_t *so,
+                                                                  int32_t *dso, int32_t *flag) {
+    __shared__ uint32_t lr[kSmallN];
+    __shared__ uint32_t stage[kSmallThreads * kSmallScanPer];
+    __shared__ uint32_t scan_lds[kSmallThreads / kWave];
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t v = tid; v < n; v += kSmallThreads) lr[v] = kInf;
+    for (uint32_t i = tid; i < nw; i += kSmallThreads) W[i] = make_uint2(0u, 0u);
+    __syncthreads();
+    bool bad = false;
+    // first positions: a round's loads are all issued before its LDS atomics
+    for (uint32_t k0 = tid; k0 < m; k0 += kSmallThreads * kSmallU) {
+        int32_t a[kSmallU], b[kSmallU];
+#pragma unroll
+        for (int j = 0; j < kSmallU; ++j) {
+            const uint32_t k = min(k0 + j * kSmallThreads, m - 1);
+            a[j] = src[k];
+            b[j] = dst[k];
+        }
+#pragma unroll
+        for (int j = 0; j < kSmallU; ++j) {
+            const uint32_t k = k0 + j * kSmallThreads;
+            if (k >= m) break;
+            const uint32_t pa = INTERLEAVED ? 2 * k : k, pb = INTERLEAVED ? 2 * k + 1 : m + k;
+            if ((uint32_t)a[j] < n) {
+                if (pa < lr[a[j]]) lower<RACY>(&lr[a[j]], pa);
+            } else {
+                bad = true;
+            }
+            if ((uint32_t)b[j] < n) {
+                if (pb < lr[b[j]]) lower<RACY>(&lr[b[j]], pb);
+            } else {
+                bad = true;
+            }
+        }
+    }
+    __syncthreads();
+    // keys into the bitmap (never-occurring vertices after every position)
+    for (uint32_t v = tid; v < n; v += kSmallThreads) {
+        uint32_t p = lr[v];
+        if (p == kInf) p = 2 * m + v;
+        lr[v] = p;
+        atomicOr(&W[p >> 5].x, 1u << (p & 31));
+    }
+    __syncthreads();
+    // W[i].y = keys in words [0, i): rounds of kSmallThreads * kSmallScanPer
+    // words, each thread a run of kSmallScanPer consecutive words
+    uint32_t carry = 0;
+    for (uint32_t w0 = 0; w0 < nw; w0 += kSmallThreads * kSmallScanPer) {
+#pragma unroll
+        for (int j = 0; j < kSmallScanPer; ++j) {
+            const uint32_t i = w0 + j * kSmallThreads + tid;
+            stage[j * kSmallThreads + tid] = i < nw ? ld_l2(&W[i].x) : 0u;
+        }
+        __syncthreads();
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int j = 0; j < kSmallScanPer; ++j) cnt += __popc(stage[tid * kSmallScanPer + j]);
+        uint32_t total;
+        uint32_t run = carry + block_exclusive_scan<kSmallThreads>(cnt, OpSum{}, scan_lds, total);
+#pragma unroll
+        for (int j = 0; j < kSmallScanPer; ++j) {
+            const uint32_t bits = stage[tid * kSmallScanPer + j];
+            stage[tid * kSmallScanPer + j] = run;
+            run += __popc(bits);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kSmallScanPer; ++j) {
+            const uint32_t i = w0 + j * kSmallThreads + tid;
+            if (i < nw) W[i].y = stage[j * kSmallThreads + tid];
+        }
+        carry += total;
+        __syncthreads();
+    }
+    // ranks; each thread rewrites only its own vertices' LDS entries
+    for (uint32_t v = tid; v < n; v += kSmallThreads) {
+        const uint32_t p = lr[v];
+        const uint2 w = ld_l2_2(&W[p >> 5]);
+        const uint32_t k = w.y + __popc(w.x & ((1u << (p & 31)) - 1u));
+        perm[v] = (int32_t)k;
+        if (order) order[k] = (int32_t)v;
+        lr[v] = k;
+    }
+    if (so) {
+        __syncthreads();
+        for (uint32_t k0 = tid; k0 < m; k0 += kSmallThreads * kSmallU) {
+            int32_t a[kSmallU], b[kSmallU];
+#pragma unroll
+            for (int j = 0; j < kSmallU; ++j) {
+                const uint32_t k = min(k0 + j * kSmallThreads, m - 1);
+                a[j] = src[k];
+                b[j] = dst[k];
+            }
+#pragma unroll
+            for (int j = 0; j < kSmallU; ++j) {
+                const uint32_t k = k0 + j * kSmallThreads;
+                if (k >= m) break;
+                // an out-of-range ID (flagged above) is passed through
+                so[k] = (uint32_t)a[j] < n ? (int32_t)lr[a[j]] : a[j];
+                dso[k] = (uint32_t)b[j] < n ? (int32_t)lr[b[j]] : b[j];
+            }
+        }
+    }
+    if (bad) flag_range_error(flag);
+}
+
 // ------------------------------------------------------- bucketed scatter-min
 // The direct scatter above issues one random 4-byte read of r per position;
 // for a 64 MB r those reads run at HBM random-access speed.  The bucketed path
@@ -982,6 +1120,7 @@ inline bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 // Host-side plan: which scatter path runs and the bucketed path's shape.
 struct ReorderPlan {
+    bool small;     // one workgroup, one launch (small_graph), unless BOBA_FLAG_FORCE_GENERAL
     bool bucketed;
     uint32_t nb, tiles_half, nt, region, slices, tps;
     uint32_t kbits, nblk;  // key blocks of the bucketed ranking
@@ -989,6 +1128,7 @@ struct ReorderPlan {
 
 ReorderPlan reorder_plan(int64_t n, int64_t m) {
     ReorderPlan P{};
+    P.small = small_graph(n, m);
     P.nb = ceil_div((uint64_t)n, kBucketW);
     P.tiles_half = ceil_div((uint64_t)m, kTileT);
     P.nt = 2 * P.tiles_half;
@@ -1032,7 +1172,7 @@ struct ReorderLayout {
 };
 
 ReorderLayout reorder_layout(void *ws, int64_t n, int64_t m, const ReorderPlan &P, bool with_vals = false) {
-    ReorderLayout L;
+    ReorderLayout L{};
     const uint64_t positions = 2 * (uint64_t)m + (uint64_t)n;
     L.nw = ceil_div(positions, 32);
     Carver c(ws);
@@ -1069,12 +1209,34 @@ boba_status check_sizes(int64_t m, int64_t n, bool positions) {
     return BOBA_OK;
 }
 
-// Launches the reorder; *bucketed tells which scatter path ran.
+// Which path a reorder took.
+enum ReorderPath { PATH_SMALL, PATH_BUCKETED, PATH_DIRECT };
+
+// Launches the reorder; *path tells which path ran.  so / dso (nullable): the
+// small path also writes the relabelled edges there.
 boba_status reorder_run(const int32_t *src, const int32_t *dst, uint32_t um, uint32_t un, int32_t *perm,
-                        int32_t *order, bool inter, bool racy, const ReorderPlan &P, const ReorderLayout &L,
-                        int32_t *flag, hipStream_t stream, bool *bucketed_out) {
+                        int32_t *order, bool inter, bool racy, bool general, const ReorderPlan &P,
+                        const ReorderLayout &L, int32_t *flag, hipStream_t stream, ReorderPath *path,
+                        int32_t *so = nullptr,
+                        int32_t *dso = nullptr) {
+    if (P.small && !general) {
+        *path = PATH_SMALL;
+        if (inter && racy)
+            BOBA_LAUNCH("small_reorder", (k_small_reorder<true, true>), dim3(1), dim3(kSmallThreads), stream, src, dst,
+                        um, un, L.W, L.nw, perm, order, so, dso, flag);
+        else if (inter)
+            BOBA_LAUNCH("small_reorder", (k_small_reorder<true, false>), dim3(1), dim3(kSmallThreads), stream, src,
+                        dst, um, un, L.W, L.nw, perm, order, so, dso, flag);
+        else if (racy)
+            BOBA_LAUNCH("small_reorder", (k_small_reorder<false, true>), dim3(1), dim3(kSmallThreads), stream, src,
+                        dst, um, un, L.W, L.nw, perm, order, so, dso, flag);
+        else
+            BOBA_LAUNCH("small_reorder", (k_small_reorder<false, false>), dim3(1), dim3(kSmallThreads), stream, src,
+                        dst, um, un, L.W, L.nw, perm, order, so, dso, flag);
+        return BOBA_OK;
+    }
     const bool bucketed = P.bucketed && aligned16(src) && aligned16(dst);
-    *bucketed_out = bucketed;
+    *path = bucketed ? PATH_BUCKETED : PATH_DIRECT;
     const uint32_t tail = 2 * um;
     if (bucketed) {
         BOBA_LAUNCH("bucket_split", k_bucket_split, dim3(P.nt < device_cus() ? P.nt : device_cus()),
@@ -1185,7 +1347,7 @@ boba_status relabel_run(const int32_t *src, const int32_t *dst, uint32_t um, con
 boba_status reorder_args(const int32_t *src, const int32_t *dst, int64_t m, int64_t n, int32_t *perm, uint32_t flags,
                          const char *who) {
     if (boba_status e = check_sizes(m, n, true)) return e;
-    if (flags & ~(BOBA_FLAG_INTERLEAVED | BOBA_FLAG_RACY))
+    if (flags & ~(BOBA_FLAG_INTERLEAVED | BOBA_FLAG_RACY | BOBA_FLAG_FORCE_GENERAL))
         return fail(BOBA_ERR_ARG, "%s: unknown flags 0x%x", who, flags);
     if (m > 0 && (!src || !dst)) return fail(BOBA_ERR_ARG, "%s: src/dst is NULL", who);
     if (m > 0 && n == 0) return fail(BOBA_ERR_ARG, "%s: edges given but n = 0", who);
@@ -1216,10 +1378,9 @@ extern "C" boba_status boba_reorder(const int32_t *src, const int32_t *dst, int6
     if (!flag) return BOBA_ERR_HIP;
     const ReorderPlan P = reorder_plan(n, m);
     const ReorderLayout L = reorder_layout(ws, n, m, P);
-    bool bucketed = false;
+    ReorderPath path;
     return reorder_run(src, dst, (uint32_t)m, (uint32_t)n, perm, order, flags & BOBA_FLAG_INTERLEAVED,
-                       flags & BOBA_FLAG_RACY, P, L, flag,
-                       stream, &bucketed);
+                       flags & BOBA_FLAG_RACY, flags & BOBA_FLAG_FORCE_GENERAL, P, L, flag, stream, &path);
 }
 
 extern "C" size_t boba_reorder_relabel_workspace(int64_t n, int64_t m) {
@@ -1244,13 +1405,14 @@ extern "C" boba_status boba_reorder_relabel(const int32_t *src, const int32_t *d
     const uint32_t um = (uint32_t)m, un = (uint32_t)n;
     const ReorderPlan P = reorder_plan(n, m);
     const ReorderLayout L = reorder_layout(ws, n, m, P, true);
-    bool bucketed = false;
+    ReorderPath path;
     if (boba_status e = reorder_run(src, dst, um, un, perm, order, flags & BOBA_FLAG_INTERLEAVED,
-                                    flags & BOBA_FLAG_RACY, P, L, flag, stream,
-                                    &bucketed))
+                                    flags & BOBA_FLAG_RACY, flags & BOBA_FLAG_FORCE_GENERAL, P, L, flag, stream,
+                                    &path, m > 0 ? src_out : nullptr,
+                                    m > 0 ? dst_out : nullptr))
         return e;
-    if (m == 0) return BOBA_OK;
-    if (!bucketed) return relabel_run(src, dst, um, perm, un, src_out, dst_out, flag, stream);
+    if (m == 0 || path == PATH_SMALL) return BOBA_OK;
+    if (path == PATH_DIRECT) return relabel_run(src, dst, um, perm, un, src_out, dst_out, flag, stream);
     BOBA_LAUNCH("bucket_relabel", k_bucket_relabel, dim3(P.nb * P.slices), dim3(kMinThreads), stream,
                 (const uint32_t *)L.recs, (const uint32_t *)L.off_t, P.nt, P.region, P.nb, P.tps, min_batch(P), un,
                 (const int32_t *)perm, L.vals);

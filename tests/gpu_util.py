@@ -35,10 +35,11 @@ def bits_equal(a, b):
     return a.shape == b.shape and np.array_equal(a.view(np.uint32), b.view(np.uint32))
 
 
-def full_path_check(g, boba, interleaved=False, check_spmv=True):
+def full_path_check(g, boba, interleaved=False, check_spmv=True, general=False):
     """Run reorder -> relabel -> CSR -> SpMV on the GPU and compare every
-    element with the oracle on the same inputs."""
-    flags = boba.BOBA_FLAG_INTERLEAVED if interleaved else 0
+    element with the oracle on the same inputs.  general: small graphs through
+    the many-workgroup reorder path instead of the one-launch path."""
+    flags = (boba.BOBA_FLAG_INTERLEAVED if interleaved else 0) | (boba.BOBA_FLAG_FORCE_GENERAL if general else 0)
     s, d = dev(g.src), dev(g.dst)
     perm, order = boba.boba_reorder(s, d, g.n, flags=flags)
     p_ref, o_ref = oracle.boba(g.src, g.dst, g.n, interleaved=interleaved)

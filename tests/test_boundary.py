@@ -79,7 +79,7 @@ def test_reorder_argument_errors(lib):
         ((FAKE, None, 10, 10, FAKE, None, FAKE, ws_need, 0, None), boba.BOBA_ERR_ARG),
         ((FAKE, FAKE, 10, 10, None, None, FAKE, ws_need, 0, None), boba.BOBA_ERR_ARG),
         ((FAKE, FAKE, 10, 10, FAKE, None, FAKE, ws_need, 0x80, None), boba.BOBA_ERR_ARG),
-        ((FAKE, FAKE, 10, 10, FAKE, None, FAKE, ws_need, 0x4, None), boba.BOBA_ERR_ARG),
+        ((FAKE, FAKE, 10, 10, FAKE, None, FAKE, ws_need, 0x8, None), boba.BOBA_ERR_ARG),
         ((FAKE, FAKE, 10, 0, FAKE, None, FAKE, ws_need, 0, None), boba.BOBA_ERR_ARG),
         ((FAKE, FAKE, 10, 10, FAKE, None, None, ws_need, 0, None), boba.BOBA_ERR_WORKSPACE),
         ((FAKE, FAKE, 10, 10, FAKE, None, FAKE, ws_need - 1, 0, None), boba.BOBA_ERR_WORKSPACE),

@@ -51,37 +51,41 @@ def test_brute_force_every_edge_order():
         for p in itertools.permutations(range(m)):
             I = I0[list(p)].astype(np.int32)
             J = J0[list(p)].astype(np.int32)
-            for inter in (False, True):
-                perm, _ = boba.boba_reorder(dev(I), dev(J), n,
-                                            flags=boba.BOBA_FLAG_INTERLEAVED if inter else 0)
+            for inter, gen in itertools.product((False, True), (False, True)):
+                flags = (boba.BOBA_FLAG_INTERLEAVED if inter else 0) | (boba.BOBA_FLAG_FORCE_GENERAL if gen else 0)
+                perm, _ = boba.boba_reorder(dev(I), dev(J), n, flags=flags)
                 assert np.array_equal(host(perm), oracle.boba(I, J, n, inter)[0])
 
 
+# general=False: the one-launch path for small graphs; True: the
+# many-workgroup path on the same graphs
+@pytest.mark.parametrize("general", [False, True])
 @pytest.mark.parametrize("m", [0, 1, 2, 3, 4, 5, 7, 8, 63, 64, 65, 1023, 4095, 4096, 4097, 16385])
-def test_ragged_edge_counts(m):
+def test_ragged_edge_counts(m, general):
     g = graphgen.small_workload("uniform", 1000, m, 100 + m)
-    full_path_check(g, boba)
-    full_path_check(g, boba, interleaved=True, check_spmv=False)
+    full_path_check(g, boba, general=general)
+    full_path_check(g, boba, interleaved=True, check_spmv=False, general=general)
 
 
-def test_degenerate_graphs():
+@pytest.mark.parametrize("general", [False, True])
+def test_degenerate_graphs(general):
     # n = 1, only self-loops
     g = graphgen.Graph("loop1", 1, np.zeros(9, np.int32), np.zeros(9, np.int32),
                        np.ones(9, np.float32), np.ones(1, np.float32))
-    full_path_check(g, boba)
+    full_path_check(g, boba, general=general)
     # all vertices isolated
     g = graphgen.Graph("iso", 777, np.zeros(0, np.int32), np.zeros(0, np.int32),
                        np.zeros(0, np.float32), graphgen.uniform_values(777, 5))
-    full_path_check(g, boba)
+    full_path_check(g, boba, general=general)
     # only self-loops, many vertices, maximum ID present
     v = np.array([999, 3, 500, 999, 0, 3], np.int32)
     g = graphgen.Graph("loops", 1000, v, v.copy(), graphgen.uniform_values(6, 6), graphgen.uniform_values(1000, 7))
-    full_path_check(g, boba)
+    full_path_check(g, boba, general=general)
     # a single hub: star listed with the centre as source
     leaves = np.random.default_rng(8).permutation(np.arange(1, 5000)).astype(np.int32)
     g = graphgen.Graph("star", 5000, np.zeros(leaves.size, np.int32), leaves,
                        graphgen.uniform_values(leaves.size, 9), graphgen.uniform_values(5000, 10))
-    full_path_check(g, boba)
+    full_path_check(g, boba, general=general)
 
 
 @pytest.mark.parametrize("kind,n,m", [("uniform", 16384, 131072), ("rmat", 1 << 16, (1 << 20) + 3),
@@ -92,17 +96,29 @@ def test_random_graphs_full_path(kind, n, m):
     full_path_check(g, boba)
 
 
-def test_uniform14_workload_full_path():
-    full_path_check(graphgen.make_workload("uniform14"), boba)
+@pytest.mark.parametrize("general", [False, True])
+def test_uniform14_workload_full_path(general):
+    full_path_check(graphgen.make_workload("uniform14"), boba, general=general)
 
 
-def test_unaligned_inputs_take_the_scalar_path():
+@pytest.mark.parametrize("n,m", [(32768, (1 << 20) - 16384), (32768, (1 << 20) - 16383), (32769, 1000),
+                                 (1, (1 << 20) - 1)])
+def test_one_launch_path_limits(n, m):
+    # the largest graphs the one-launch path takes (n = 2^15, 2m + n = 2^21),
+    # and the first ones past each limit (many-workgroup path)
+    g = graphgen.small_workload("uniform", n, m, 120 + m % 7)
+    full_path_check(g, boba, check_spmv=False)
+    full_path_check(g, boba, interleaved=True, check_spmv=False)
+
+
+@pytest.mark.parametrize("general", [False, True])
+def test_unaligned_inputs_take_the_scalar_path(general):
     g = graphgen.small_workload("rmat", 4096, 40001, 77)
     big_s = dev(np.concatenate([[0], g.src]).astype(np.int32))
     big_d = dev(np.concatenate([[0], g.dst]).astype(np.int32))
     s, d = big_s[1:], big_d[1:]
     assert s.data_ptr() % 16 != 0
-    perm, order = boba.boba_reorder(s, d, g.n)
+    perm, order = boba.boba_reorder(s, d, g.n, flags=boba.BOBA_FLAG_FORCE_GENERAL if general else 0)
     p_ref, o_ref = oracle.boba(g.src, g.dst, g.n)
     assert np.array_equal(host(perm), p_ref) and np.array_equal(host(order), o_ref)
     out_s = torch.empty(g.m + 1, dtype=torch.int32, device="cuda")[1:]
@@ -112,10 +128,11 @@ def test_unaligned_inputs_take_the_scalar_path():
     assert np.array_equal(host(out_s), s_ref) and np.array_equal(host(out_d), d_ref)
 
 
-def test_relabel_in_place():
+@pytest.mark.parametrize("general", [False, True])
+def test_relabel_in_place(general):
     g = graphgen.small_workload("rmat", 8192, 100000, 78)
     s, d = dev(g.src), dev(g.dst)
-    perm, _ = boba.boba_reorder(s, d, g.n)
+    perm, _ = boba.boba_reorder(s, d, g.n, flags=boba.BOBA_FLAG_FORCE_GENERAL if general else 0)
     boba.boba_relabel(s, d, perm, src_out=s, dst_out=d)
     s_ref, d_ref = oracle.relabel(g.src, g.dst, oracle.boba(g.src, g.dst, g.n)[0])
     assert np.array_equal(host(s), s_ref) and np.array_equal(host(d), d_ref)
@@ -230,8 +247,9 @@ def test_more_than_2_25_vertices_uses_the_direct_path():
 @pytest.mark.parametrize("n", [32767, 32768, 32769, 65536 * 3 + 1])
 def test_bucket_boundaries(n):
     g = graphgen.small_workload("uniform", n, 3 * n + 1, 85 + n)
-    full_path_check(g, boba)
-    full_path_check(g, boba, interleaved=True, check_spmv=False)
+    for general in (False, True):
+        full_path_check(g, boba, general=general)
+        full_path_check(g, boba, interleaved=True, check_spmv=False, general=general)
 
 
 @pytest.mark.parametrize("lengths", [
@@ -257,24 +275,26 @@ def test_spmv_rows_across_chunk_boundaries(lengths):
     assert np.all(np.abs(y - y_ref) <= 1e-4 * (1 + np.abs(y_ref)) + 1e-5 * np.sqrt(np.diff(rowptr)))
 
 
-def test_fused_reorder_relabel_in_place_and_unaligned():
+@pytest.mark.parametrize("general", [False, True])
+def test_fused_reorder_relabel_in_place_and_unaligned(general):
     g = graphgen.small_workload("rmat", 1 << 15, 300001, 86)
+    fl = boba.BOBA_FLAG_FORCE_GENERAL if general else 0
     p_ref, o_ref = oracle.boba(g.src, g.dst, g.n)
     s_ref, d_ref = oracle.relabel(g.src, g.dst, p_ref)
     s, d = dev(g.src), dev(g.dst)
-    perm, order, so, do = boba.boba_reorder_relabel(s, d, g.n, src_out=s, dst_out=d)  # in place
+    perm, order, so, do = boba.boba_reorder_relabel(s, d, g.n, src_out=s, dst_out=d, flags=fl)  # in place
     assert np.array_equal(host(s), s_ref) and np.array_equal(host(d), d_ref)
     assert np.array_equal(host(perm), p_ref)
     # unaligned outputs: bucketed reorder, element-wise stores
     s, d = dev(g.src), dev(g.dst)
     out_s = torch.empty(g.m + 1, dtype=torch.int32, device="cuda")[1:]
     out_d = torch.empty(g.m + 1, dtype=torch.int32, device="cuda")[1:]
-    boba.boba_reorder_relabel(s, d, g.n, src_out=out_s, dst_out=out_d)
+    boba.boba_reorder_relabel(s, d, g.n, src_out=out_s, dst_out=out_d, flags=fl)
     assert np.array_equal(host(out_s), s_ref) and np.array_equal(host(out_d), d_ref)
     # unaligned inputs: direct path
     big_s = dev(np.concatenate([[0], g.src]).astype(np.int32))[1:]
     big_d = dev(np.concatenate([[0], g.dst]).astype(np.int32))[1:]
-    perm, _, so, do = boba.boba_reorder_relabel(big_s, big_d, g.n)
+    perm, _, so, do = boba.boba_reorder_relabel(big_s, big_d, g.n, flags=fl)
     assert np.array_equal(host(so), s_ref) and np.array_equal(host(do), d_ref)
     assert boba.boba_check_device_error() == boba.BOBA_OK
 
@@ -384,7 +404,9 @@ def racy_result_is_valid(src, dst, n, perm, order, interleaved=False):
 
 
 @pytest.mark.parametrize("kind,n,m,interleaved", [("rmat", 1 << 16, 1 << 20, False), ("uniform", 70001, 300007, True),
-                                                  ("rmat", (1 << 20) + 3, 1 << 22, False)])
+                                                  ("rmat", (1 << 20) + 3, 1 << 22, False),
+                                                  ("rmat", 1 << 14, 1 << 17, False),  # one-launch path
+                                                  ("uniform", 30000, 200001, True)])
 def test_racy_flag_gives_a_valid_order(kind, n, m, interleaved):
     g = graphgen.small_workload(kind, n, m, 106 + n % 11)
     flags = boba.BOBA_FLAG_RACY | (boba.BOBA_FLAG_INTERLEAVED if interleaved else 0)
