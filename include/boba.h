@@ -96,6 +96,24 @@ BOBA_API boba_status boba_reorder(const int32_t *src, const int32_t *dst, int64_
                          int32_t *perm, int32_t *order, void *ws, size_t ws_bytes,
                          uint32_t flags, hipStream_t stream);
 
+/* boba_reorder for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * results as boba_reorder, with the workspace taken from library-owned device
+ * memory instead of a caller buffer.  That memory is a static array of
+ * BOBA_REORDER_NOALLOC_MAX_BYTES per device, held from the first call on a
+ * device until the process ends.  The call allocates nothing; it accepts a
+ * graph iff boba_reorder_workspace(n, m) <= BOBA_REORDER_NOALLOC_MAX_BYTES
+ * (e.g. 2^16 vertices with 2^20 edges, or 2^14 vertices with 2^17 edges) and
+ * otherwise returns BOBA_ERR_WORKSPACE before enqueuing anything.
+ * Every call on a device shares that device's array: calls that overlap in
+ * time on one device (two streams, two threads) race and give unspecified
+ * results; calls ordered on one stream are safe.  The array keeps the last
+ * call's contents, none of which a later call relies on.
+ *   Arguments, flags and errors as boba_reorder, without ws / ws_bytes. */
+#define BOBA_REORDER_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+BOBA_API boba_status boba_reorder_noalloc(const int32_t *src, const int32_t *dst, int64_t m, int64_t n,
+                                          int32_t *perm, int32_t *order, uint32_t flags, hipStream_t stream);
+
 /* ------------------------------------------------------------- relabel ---
  * Applies a vertex permutation to an edge list (the step between BOBA and CSR
  * construction, Sec. 5.3): src_out[k] = perm[src[k]], dst_out[k] = perm[dst[k]].

@@ -30,6 +30,7 @@ PROTOTYPES = {
     "boba_check_device_error": (_I32, [_P, _P]),
     "boba_reorder_workspace": (_SZ, [_I64, _I64]),
     "boba_reorder": (_I32, [_P, _P, _I64, _I64, _P, _P, _P, _SZ, _U32, _P]),
+    "boba_reorder_noalloc": (_I32, [_P, _P, _I64, _I64, _P, _P, _U32, _P]),
     "boba_relabel": (_I32, [_P, _P, _I64, _P, _I64, _P, _P, _P]),
     "boba_relabel_bucketed_workspace": (_SZ, [_I64, _I64]),
     "boba_relabel_bucketed": (_I32, [_P, _P, _I64, _P, _I64, _P, _P, _P, _SZ, _P]),
@@ -135,6 +136,28 @@ def boba_reorder(src, dst, n: int, *, with_order: bool = True, flags: int = 0, w
     _check(load().boba_reorder(_ptr(src), _ptr(dst), m, n, _ptr(perm), _ptr(order) if with_order else None,
                                _ptr(ws), ws.numel(), flags, _stream(stream)))
     return perm, (order if with_order else None)
+
+
+BOBA_REORDER_NOALLOC_MAX_BYTES = 64 << 20  # include/boba.h
+
+
+def boba_reorder_noalloc(src, dst, n: int, perm, order=None, *, flags: int = 0, stream=None):
+    """boba_reorder with the library's static scratch as workspace: writes
+    perm (and order, if given) and allocates nothing, so the caller passes
+    both outputs."""
+    _dev_i32(src, "src")
+    _dev_i32(dst, "dst")
+    _dev_i32(perm, "perm")
+    if order is not None:
+        _dev_i32(order, "order")
+    m = src.numel()
+    if dst.numel() != m:
+        raise ValueError("src and dst differ in length")
+    if perm.numel() < n or (order is not None and order.numel() < n):
+        raise ValueError("perm/order hold fewer than n entries")
+    _check(load().boba_reorder_noalloc(_ptr(src), _ptr(dst), m, n, _ptr(perm), _ptr(order), flags,
+                                       _stream(stream)))
+    return perm, order
 
 
 def boba_relabel(src, dst, perm, *, src_out=None, dst_out=None, stream=None):

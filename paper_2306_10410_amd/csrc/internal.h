@@ -46,6 +46,12 @@ boba_status check_launch(const char *what);
 // Optional event timing around launches (see boba_timing_enable).
 int timing_begin(const char *name, hipStream_t s);
 void timing_end(int token, hipStream_t s);
+// While one is alive, launches on this thread are not timed (creating the
+// events can allocate; the allocation-free entry point must not).
+struct TimingSuspend {
+    TimingSuspend();
+    ~TimingSuspend();
+};
 
 // Launches a kernel (parenthesise template kernels), times it when timing is
 // on, and returns BOBA_ERR_HIP from the enclosing function if the launch fails.

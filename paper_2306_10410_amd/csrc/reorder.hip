@@ -20,6 +20,8 @@
 //     rank      perm[v] = number of set bits before key(v)
 //   The direct path's bitmap holds, per 32 positions, {bits, exclusive prefix
 //   popcount} as one uint2 so that rank needs one 8-byte load per vertex.
+#include <mutex>
+
 #include "internal.h"
 #include "scan.h"
 
@@ -1376,6 +1378,61 @@ extern "C" boba_status boba_reorder(const int32_t *src, const int32_t *dst, int6
                     need, ws_bytes, ws);
     int32_t *flag = range_flag();
     if (!flag) return BOBA_ERR_HIP;
+    const ReorderPlan P = reorder_plan(n, m);
+    const ReorderLayout L = reorder_layout(ws, n, m, P);
+    ReorderPath path;
+    return reorder_run(src, dst, (uint32_t)m, (uint32_t)n, perm, order, flags & BOBA_FLAG_INTERLEAVED,
+                       flags & BOBA_FLAG_RACY, flags & BOBA_FLAG_FORCE_GENERAL, P, L, flag, stream, &path);
+}
+
+// ------------------------------------------------ allocation-free reorder
+// Workspace of boba_reorder_noalloc.  In host code this name is only a
+// stand-in for the device array: the device address comes from
+// hipGetSymbolAddress, once per device (each device holds its own copy).
+static __device__ __align__(256) unsigned char scratch[BOBA_REORDER_NOALLOC_MAX_BYTES];
+
+namespace {
+constexpr int kScratchDevices = 64;
+void *g_scratch_ptr[kScratchDevices] = {};
+std::mutex g_scratch_mu;
+
+// Device address of this device's scratch (nullptr and a message on failure).
+void *scratch_ptr() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchDevices) {
+        fail(BOBA_ERR_HIP, "boba_reorder_noalloc: hipGetDevice failed");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            fail(BOBA_ERR_HIP, "boba_reorder_noalloc: hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" boba_status boba_reorder_noalloc(const int32_t *src, const int32_t *dst, int64_t m, int64_t n,
+                                            int32_t *perm, int32_t *order, uint32_t flags, hipStream_t stream) {
+    clear_error();
+    if (boba_status e = reorder_args(src, dst, m, n, perm, flags, "boba_reorder_noalloc")) return e;
+    if (n == 0) return BOBA_OK;
+    const size_t need = boba_reorder_workspace(n, m);
+    if (need > BOBA_REORDER_NOALLOC_MAX_BYTES)
+        return fail(BOBA_ERR_WORKSPACE,
+                    "boba_reorder_noalloc: n=%lld, m=%lld needs %zu bytes of workspace; the static scratch "
+                    "holds %zu",
+                    (long long)n, (long long)m, need, (size_t)BOBA_REORDER_NOALLOC_MAX_BYTES);
+    void *ws = scratch_ptr();
+    if (!ws) return BOBA_ERR_HIP;
+    int32_t *flag = range_flag();
+    if (!flag) return BOBA_ERR_HIP;
+    TimingSuspend no_events;
     const ReorderPlan P = reorder_plan(n, m);
     const ReorderLayout L = reorder_layout(ws, n, m, P);
     ReorderPath path;

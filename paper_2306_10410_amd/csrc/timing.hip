@@ -21,6 +21,7 @@ std::mutex g_mu;
 bool g_on = false;
 std::vector<Record> g_records;
 std::vector<hipEvent_t> g_pool;
+thread_local int g_suspended = 0;
 
 hipEvent_t take_event() {
     if (!g_pool.empty()) {
@@ -35,7 +36,11 @@ hipEvent_t take_event() {
 
 }  // namespace
 
+TimingSuspend::TimingSuspend() { ++g_suspended; }
+TimingSuspend::~TimingSuspend() { --g_suspended; }
+
 int timing_begin(const char *name, hipStream_t s) {
+    if (g_suspended) return -1;
     std::lock_guard<std::mutex> lock(g_mu);
     if (!g_on) return -1;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;

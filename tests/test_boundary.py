@@ -94,6 +94,29 @@ def test_reorder_argument_errors(lib):
     assert lib.boba_last_error().decode() == ""
 
 
+def test_reorder_noalloc_rejects_on_the_host(lib):
+    cap = boba.BOBA_REORDER_NOALLOC_MAX_BYTES
+    # the largest sizes in the header's examples fit, a graph beyond the static scratch does not
+    assert lib.boba_reorder_workspace(1 << 16, 1 << 20) <= cap
+    assert lib.boba_reorder_workspace(1 << 14, 1 << 17) <= cap
+    n, m = 1 << 20, 1 << 23
+    assert lib.boba_reorder_workspace(n, m) > cap
+    rc, msg = status_and_msg(lib, lib.boba_reorder_noalloc(FAKE, FAKE, m, n, FAKE, None, 0, None))
+    assert rc == boba.BOBA_ERR_WORKSPACE and "static scratch" in msg
+    cases = [
+        ((FAKE, FAKE, -1, 10, FAKE, None, 0, None), boba.BOBA_ERR_ARG),
+        ((FAKE, FAKE, 1 << 31, 10, FAKE, None, 0, None), boba.BOBA_ERR_OVERFLOW),
+        ((None, FAKE, 10, 10, FAKE, None, 0, None), boba.BOBA_ERR_ARG),
+        ((FAKE, FAKE, 10, 10, None, None, 0, None), boba.BOBA_ERR_ARG),
+        ((FAKE, FAKE, 10, 10, FAKE, None, 0x80, None), boba.BOBA_ERR_ARG),
+        ((FAKE, FAKE, 10, 0, FAKE, None, 0, None), boba.BOBA_ERR_ARG),
+    ]
+    for args, want in cases:
+        rc, msg = status_and_msg(lib, lib.boba_reorder_noalloc(*args))
+        assert rc == want and msg, (args, rc, msg)
+    assert lib.boba_reorder_noalloc(None, None, 0, 0, None, None, 0, None) == boba.BOBA_OK
+
+
 def test_relabel_csr_spmv_argument_errors(lib):
     assert lib.boba_relabel(FAKE, FAKE, -1, FAKE, 5, FAKE, FAKE, None) == boba.BOBA_ERR_ARG
     assert lib.boba_relabel(FAKE, FAKE, 1 << 31, FAKE, 5, FAKE, FAKE, None) == boba.BOBA_ERR_OVERFLOW
