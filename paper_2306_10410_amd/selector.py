@@ -15,7 +15,9 @@ Labels are measured by the method itself on the GPU:
     T_never  = t(coo_to_csr on input labels) + t(spmv_iters SpMVs on it)
     T_always = t(boba_reorder_relabel) + t(coo_to_csr on BOBA labels)
                + t(spmv_iters SpMVs on it)
-each the median of `reps` HIP-event timings (the SpMVs run back to back).  Training uses the library's own
+each the median of `reps` HIP-event timings (the SpMVs run back to back; the
+two paths alternate in going first, each after an untimed lead-in of small
+kernels).  Training uses the library's own
 backward and Adam kernels.
 """
 from __future__ import annotations
@@ -61,27 +63,51 @@ def measure_paths(src, dst, val, x, n, *, reps=5, spmv_iters=SPMV_ITERS, ws=None
     ws_r = torch.empty(max(1, boba.boba_reorder_relabel_workspace(n, m)), dtype=torch.uint8, device=dev)
     ws_c = torch.empty(max(1, boba.coo_to_csr_workspace(n, m)), dtype=torch.uint8, device=dev)
     ws_s = torch.empty(max(1, boba.spmv_csr_workspace(n, m)), dtype=torch.uint8, device=dev)
-    # the SpMV iterations run back to back between two events, as a solver
-    # would run them
-    t = {k: [] for k in ("csr_in", "spmv_in", "reorder_relabel", "csr_boba", "spmv_boba")}
-    for _ in range(reps + 1):  # first round warms up
-        e = _events(torch, 6)
+    # The SpMV iterations run back to back between two events, as a solver
+    # would run them.  Each path is preceded by a short untimed burst of small
+    # kernels, and the two paths take turns going first: the first kernels
+    # after the host's synchronisation run slower (clocks, an idle queue),
+    # which would otherwise count against whichever path always came first.
+    lead = torch.empty(1 << 16, dtype=torch.float32, device=dev)
+
+    def lead_in():
+        for _ in range(4):
+            lead.fill_(0.0)
+
+    def never(e):
+        lead_in()
         e[0].record()
         boba.coo_to_csr(src, dst, val, n, ws=ws_c, out=(rp, col, vv))
         e[1].record()
         for _ in range(spmv_iters):
             boba.spmv_csr(rp, col, vv, x, y=y, ws=ws_s)
         e[2].record()
+
+    def always(e):
+        lead_in()
+        e[0].record()
         boba.boba_reorder_relabel(src, dst, n, ws=ws_r, perm=perm, order=order, src_out=s2, dst_out=d2)
-        e[3].record()
+        e[1].record()
         boba.coo_to_csr(s2, d2, val, n, ws=ws_c, out=(rp, col, vv))
-        e[4].record()
+        e[2].record()
         for _ in range(spmv_iters):
             boba.spmv_csr(rp, col, vv, x, y=y, ws=ws_s)  # x in any labelling: same access pattern cost
-        e[5].record()
+        e[3].record()
+
+    t = {k: [] for k in ("csr_in", "spmv_in", "reorder_relabel", "csr_boba", "spmv_boba")}
+    for rnd in range(reps + 1):  # first round warms up
+        en, ea = _events(torch, 3), _events(torch, 4)
+        if rnd % 2 == 0:
+            never(en)
+            always(ea)
+        else:
+            always(ea)
+            never(en)
         torch.cuda.synchronize()
-        for i, k in enumerate(t):
-            t[k].append(e[i].elapsed_time(e[i + 1]))
+        for k, (a, b) in (("csr_in", (en[0], en[1])), ("spmv_in", (en[1], en[2])),
+                          ("reorder_relabel", (ea[0], ea[1])), ("csr_boba", (ea[1], ea[2])),
+                          ("spmv_boba", (ea[2], ea[3]))):
+            t[k].append(a.elapsed_time(b))
     med = {k: float(np.median(v[1:])) for k, v in t.items()}
     med["never"] = med["csr_in"] + med["spmv_in"]
     med["always"] = med["reorder_relabel"] + med["csr_boba"] + med["spmv_boba"]
@@ -180,9 +206,14 @@ def fold_standardisation(params, mu, sigma):
     return p.astype(np.float32)
 
 
-def train(X, y, *, epochs=200, batch=256, lr=1e-3, seed=0, log=None):
+def train(X, y, *, epochs=200, batch=256, lr=1e-3, seed=0, log=None, weights=None):
     """Adam on mean squared error with the library's kernels.  Returns
-    (deployable params on raw features, mu, sigma, loss history)."""
+    (deployable params on raw features, mu, sigma, loss history).
+
+    weights (optional, one per graph): minibatch rows are drawn with
+    probability proportional to them (with replacement, N draws per epoch)
+    instead of a plain shuffle.  With weights = |T_never - T_always| the
+    regression spends its capacity where a wrong decision costs time."""
     import torch
 
     from . import boba
@@ -203,8 +234,12 @@ def train(X, y, *, epochs=200, batch=256, lr=1e-3, seed=0, log=None):
     N = X.shape[0]
     step = 0
     hist = []
+    prob = None
+    if weights is not None:
+        w = np.asarray(weights, np.float64)
+        prob = w / w.sum()
     for ep in range(epochs):
-        idx = rng.permutation(N)
+        idx = rng.permutation(N) if prob is None else rng.choice(N, size=N, p=prob)
         for b0 in range(0, N, batch):
             sel = idx[b0:b0 + batch]  # minibatch rows assembled on the host, then copied
             xb = torch.from_numpy(np.ascontiguousarray(Xs[sel])).to(dev)
@@ -404,6 +439,11 @@ def main(argv=None):
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--out", default="selector_model.npz")
     ap.add_argument("--data-out", default="selector_data.npz")
+    ap.add_argument("--weighted", type=int, default=1,
+                    help="draw training minibatches in proportion to |T_never - T_always| (0: plain shuffle)")
+    ap.add_argument("--from-data", default=None,
+                    help="train on the features, timings and labels saved by an earlier run (--data-out) "
+                         "instead of measuring the graphs again")
     ap.add_argument("--eval-model", default=None,
                     help="measure the held-out graphs only and evaluate this saved model (no training)")
     args = ap.parse_args(argv)
@@ -414,6 +454,8 @@ def main(argv=None):
         k = args.large
         tr_specs += selector_specs(k, graphgen.BASE_SEED + 52, args.log2_hi, args.large_log2_hi)
         ho_specs += selector_specs(max(1, k // 8), graphgen.BASE_SEED + 53, args.log2_hi, args.large_log2_hi)
+    if args.from_data:
+        return train_and_report(args, log, *load_data(args.from_data))
     pool = start_pool(args.workers) if args.workers > 1 else None  # before the GPU is touched
     t0 = time.perf_counter()
     warm_up(log)
@@ -444,7 +486,26 @@ def main(argv=None):
     if pool is not None:
         pool.shutdown()
     log(f"datasets in {time.perf_counter() - t0:.1f}s; train labels: {np.mean(ytr > 0):.3f} reorder-pays")
-    params, mu, sigma, hist = train(Xtr, ytr, epochs=args.epochs, log=log)
+    np.savez(args.data_out, Xtr=Xtr, ytr=ytr, Xho=Xho, yho=yho,
+             rows_tr=np.frombuffer(json.dumps(rtr).encode(), np.uint8),
+             rows_ho=np.frombuffer(json.dumps(rho).encode(), np.uint8))
+    return train_and_report(args, log, Xtr, ytr, rtr, Xho, yho, rho)
+
+
+def load_data(path):
+    z = np.load(path)
+    return (z["Xtr"], z["ytr"], json.loads(bytes(z["rows_tr"]).decode()), z["Xho"], z["yho"],
+            json.loads(bytes(z["rows_ho"]).decode()))
+
+
+def train_and_report(args, log, Xtr, ytr, rtr, Xho, yho, rho):
+    """Trains on the training graphs, picks the size gate on them, saves the
+    model and prints the held-out evaluation."""
+    # a graph's weight is what the wrong choice would cost on it, with a floor
+    # so that no graph is never seen
+    gap = np.abs(np.array([r["never"] - r["always"] for r in rtr]))
+    weights = gap + 0.05 * float(np.median(gap)) if args.weighted else None
+    params, mu, sigma, hist = train(Xtr, ytr, epochs=args.epochs, log=log, weights=weights)
     t_inf = time_inference(params)
     import torch
 
@@ -453,12 +514,10 @@ def main(argv=None):
     gate = choose_gate(pred_tr, rtr, t_inf)
     log(f"size gate: log2(1 + m) >= {gate:.3f}")
     os.makedirs(os.path.dirname(args.out) or ".", exist_ok=True)
-    save_model(args.out, params, mu, sigma, {"train": args.train, "epochs": args.epochs}, gate=gate)
-    np.savez(args.data_out, Xtr=Xtr, ytr=ytr, Xho=Xho, yho=yho,
-             rows_tr=np.frombuffer(json.dumps(rtr).encode(), np.uint8),
-             rows_ho=np.frombuffer(json.dumps(rho).encode(), np.uint8))
+    save_model(args.out, params, mu, sigma, {"train": len(rtr), "epochs": args.epochs,
+                                             "weighted": bool(args.weighted)}, gate=gate)
     res = evaluate(params, Xho, rho, t_inf, gate)
-    res.update({"train_graphs": args.train, "train_mse": hist[-1], "t_infer_ms": t_inf,
+    res.update({"train_graphs": len(rtr), "train_mse": hist[-1], "t_infer_ms": t_inf, "weighted": bool(args.weighted),
                 "t_feat_ms_median": float(np.median([r["t_feat"] for r in rho]))})
     print(json.dumps(res), flush=True)
     return 0
