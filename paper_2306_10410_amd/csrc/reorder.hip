@@ -1041,7 +1041,9 @@ __global__ __launch_bounds__(kMinThreads) void k_rank_perm(const uint2 *__restri
     __shared__ uint32_t obs[kPermChunk];      // where the bucket's slice of each key block starts in E
     __shared__ uint32_t flags[kBucketW / 32];
     __shared__ uint32_t scan_lds[kMinThreads / kWave];
-    const uint32_t b = blockIdx.x;
+    // neighbouring buckets on one XCD: their slices of a key block lie side by
+    // side in E and are read through the same L2 (0.12 -> 0.106 ms at RMAT-24)
+    const uint32_t b = xcd_work_index(blockIdx.x, gridDim.x);
     const uint32_t v0 = b * kBucketW;
     const uint32_t cntv = min(kBucketW, n - v0);
     const uint32_t lane = threadIdx.x & (kWave - 1);
