@@ -15,7 +15,7 @@
 // rounded to FP32.  No value is used as an index, so any input is safe.
 //
 // MLP parameters, row-major, FP32: W1[64][16] b1[64] W2[64][64] b2[64] W3[1][64] b3[1].
-// Forward: one thread per sample, weights staged in LDS.  Backward: per-sample
+// Forward: one wavefront per sample, a lane per hidden unit.  Backward: per-sample
 // activations and deltas, then one thread per parameter summing over the batch
 // in sample order (deterministic).  Adam: elementwise with bias correction.
 #include <math.h>
@@ -156,8 +156,21 @@ __global__ __launch_bounds__(kT) void k_feat_stats(const int32_t *__restrict__ s
     }
 }
 
-__global__ void k_feat_final(const uint64_t *__restrict__ st, uint32_t m, uint32_t n, float *__restrict__ f) {
-    if (threadIdx.x != 0) return;
+// One wavefront: lane w < 64 holds window w's counters; their sums over the
+// windows are exact integers (wavefront reductions), so each mean is one FP64
+// division of an exact count; lane 0 combines everything.
+__global__ __launch_bounds__(kWave) void k_feat_final(const uint64_t *__restrict__ st, uint32_t m, uint32_t n,
+                                                      float *__restrict__ f) {
+    static_assert(kWin == kWave, "one window per lane");
+    const uint32_t lane = threadIdx.x;
+    uint64_t sum[kWinStats];
+#pragma unroll
+    for (int q = 0; q < kWinStats; ++q) {
+        uint64_t x = m > 0 ? st[(size_t)lane * kWinStats + q] : 0;
+        for (int d = kWave / 2; d >= 1; d >>= 1) x += __shfl_xor(x, d, kWave);
+        sum[q] = x;
+    }
+    if (lane != 0) return;
     const double dn = (double)n, dm = (double)m;
     double F[16] = {};
     F[0] = log2(1.0 + dn);
@@ -166,23 +179,18 @@ __global__ void k_feat_final(const uint64_t *__restrict__ st, uint32_t m, uint32
     if (m > 0) {
         const double P = (double)kSpread * (kSpread - 1) / 2.0;
         for (int side = 0; side < 2; ++side) {
-            const uint64_t *s = st + (size_t)kWin * kWinStats + side * kSpreadStats;
-            F[3 + side] = log2(1.0 + dn * (double)s[0] / P);
-            F[5 + side] = log2(1.0 + dn * (double)s[1] / kSpread);
-            F[7 + side] = (double)s[2] / kSpread;
+            const uint64_t *sp = st + (size_t)kWin * kWinStats + side * kSpreadStats;
+            F[3 + side] = log2(1.0 + dn * (double)sp[0] / P);
+            F[5 + side] = log2(1.0 + dn * (double)sp[1] / kSpread);
+            F[7 + side] = (double)sp[2] / kSpread;
         }
         const double L = (double)min((uint32_t)kWinLen, m);
-        double acc[7] = {};
-        for (int w = 0; w < kWin; ++w) {
-            const uint64_t *s = st + (size_t)w * kWinStats;
-            acc[0] += (double)s[0] / (L * (n > 0 ? dn : 1.0));
-            acc[1] += (double)s[1] / L;
-            acc[2] += (double)s[2] / L;
-            if (L > 1) {
-                for (int q = 3; q < 7; ++q) acc[q] += (double)s[q] / (L - 1.0);
-            }
+        F[9] = (double)sum[0] / (L * (n > 0 ? dn : 1.0) * kWin);
+        F[10] = (double)sum[1] / (L * kWin);
+        F[11] = (double)sum[2] / (L * kWin);
+        if (L > 1) {
+            for (int q = 3; q < 7; ++q) F[9 + q] = (double)sum[q] / ((L - 1.0) * kWin);
         }
-        for (int q = 0; q < 7; ++q) F[9 + q] = acc[q] / kWin;
     }
     for (int q = 0; q < 16; ++q) f[q] = (float)F[q];
 }
@@ -193,31 +201,35 @@ constexpr int OW1 = 0, OB1 = OW1 + H * IN, OW2 = OB1 + H, OB2 = OW2 + H * H, OW3
 constexpr int NP = OB3 + 1;  // 5313
 constexpr int kMT = 256;
 
+// One wavefront per sample, lane o owning hidden unit o of both layers: each
+// dot product runs in input order in its lane, the output sums the 64 lanes'
+// terms with a fixed shuffle tree.  The weights come straight from global
+// memory (21 KB, cache-resident after the first sample).
+constexpr int kFwdWaves = kMT / kWave;  // samples per workgroup
+
 __global__ __launch_bounds__(kMT) void k_mlp_forward(const float *__restrict__ P, const float *__restrict__ X,
                                                      int32_t B, float *__restrict__ yhat) {
-    __shared__ float w[NP];
-    for (int i = threadIdx.x; i < NP; i += kMT) w[i] = P[i];
-    __syncthreads();
-    const int b = blockIdx.x * kMT + threadIdx.x;
-    if (b >= B) return;
-    float x[IN], h1[H];
+    static_assert(H == kWave, "one hidden unit per lane");
+    __shared__ float h1s[kFwdWaves][H];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int b = blockIdx.x * kFwdWaves + wave;
+    if (b >= B) return;  // wave-uniform; no barrier follows
+    float x[IN];
 #pragma unroll
     for (int i = 0; i < IN; ++i) x[i] = X[(size_t)b * IN + i];
+    float s = P[OB1 + lane];
 #pragma unroll
-    for (int o = 0; o < H; ++o) {
-        float s = w[OB1 + o];
-#pragma unroll
-        for (int i = 0; i < IN; ++i) s = fmaf(w[OW1 + o * IN + i], x[i], s);
-        h1[o] = s > 0.f ? s : 0.f;
-    }
-    float out = w[OB3];
-    for (int o = 0; o < H; ++o) {
-        float s = w[OB2 + o];
-#pragma unroll
-        for (int i = 0; i < H; ++i) s = fmaf(w[OW2 + o * H + i], h1[i], s);
-        out = fmaf(w[OW3 + o], s > 0.f ? s : 0.f, out);
-    }
-    yhat[b] = out;
+    for (int i = 0; i < IN; ++i) s = fmaf(P[OW1 + lane * IN + i], x[i], s);
+    h1s[wave][lane] = s > 0.f ? s : 0.f;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float z = P[OB2 + lane];
+#pragma unroll 16
+    for (int i = 0; i < H; ++i) z = fmaf(P[OW2 + lane * H + i], h1s[wave][i], z);
+    float t = P[OW3 + lane] * (z > 0.f ? z : 0.f);
+    for (int d = kWave / 2; d >= 1; d >>= 1) t += __shfl_xor(t, d, kWave);
+    if (lane == 0) yhat[b] = P[OB3] + t;
 }
 
 // Per sample: h1, h2 and the deltas g1 = dL/dz1, g2 = dL/dz2, go = dL/dout.
@@ -335,7 +347,7 @@ extern "C" boba_status boba_graph_features(const int32_t *src, const int32_t *ds
     if (m > 0) {
         BOBA_LAUNCH("feat_stats", k_feat_stats, dim3(kWin + 2), dim3(kT), stream, src, dst, um, st);
     }
-    BOBA_LAUNCH("feat_final", k_feat_final, dim3(1), dim3(64), stream, (const uint64_t *)st, um, (uint32_t)n, feat16);
+    BOBA_LAUNCH("feat_final", k_feat_final, dim3(1), dim3(kWave), stream, (const uint64_t *)st, um, (uint32_t)n, feat16);
     return BOBA_OK;
 }
 
@@ -347,7 +359,7 @@ extern "C" boba_status boba_mlp_forward(const float *params, const float *X, int
     if (B < 0) return fail(BOBA_ERR_ARG, "boba_mlp_forward: negative batch");
     if (B == 0) return BOBA_OK;
     if (!params || !X || !yhat) return fail(BOBA_ERR_ARG, "boba_mlp_forward: NULL pointer");
-    BOBA_LAUNCH("mlp_forward", k_mlp_forward, dim3(ceil_div(B, kMT)), dim3(kMT), stream, params, X, B, yhat);
+    BOBA_LAUNCH("mlp_forward", k_mlp_forward, dim3(ceil_div(B, kFwdWaves)), dim3(kMT), stream, params, X, B, yhat);
     return BOBA_OK;
 }
 
