@@ -135,3 +135,29 @@ def test_a_wait_that_gives_up_is_reported_as_a_timeout():
     check_against_oracle(eo, vo, src, dst, host(plan.perm), host(plan.order), host(plan.src_out), host(plan.dst_out))
     assert boba.boba_check_device_error() == boba.BOBA_OK
     plan.destroy()
+
+
+@pytest.mark.timeout(900)
+def test_full_batch_config_against_the_oracle():
+    # the benchmark's batch: 512 graphs, n = 2^U(10,18), edge factor U{4..32},
+    # half RMAT half geometric (about 493M edges), default tuning, two replays;
+    # every graph checked against the oracle (generated with threads: this
+    # process already uses the GPU)
+    from concurrent.futures import ThreadPoolExecutor
+    specs = graphgen.batch_specs(512)
+    with ThreadPoolExecutor(16) as ex:
+        parts = list(ex.map(graphgen.make_batch_graph, specs))
+    m = np.array([p[0].size for p in parts], np.int64)
+    eo = np.concatenate([[0], np.cumsum(m)]).astype(np.int64)
+    vo = np.concatenate([[0], np.cumsum([s.n for s in specs])]).astype(np.int64)
+    src = np.concatenate([p[0] for p in parts])
+    dst = np.concatenate([p[1] for p in parts])
+    del parts
+    print(f"batch: {len(specs)} graphs, m={int(eo[-1])} n={int(vo[-1])}", flush=True)
+    plan = boba.BatchPlan(eo, vo, dev(src), dev(dst))
+    plan.launch()
+    plan.launch()
+    check_against_oracle(eo, vo, src, dst, host(plan.perm), host(plan.order), host(plan.src_out),
+                         host(plan.dst_out))
+    assert boba.boba_check_device_error() == boba.BOBA_OK
+    plan.destroy()
