@@ -816,6 +816,7 @@ def bench_selector(sel_data):
     t0 = time.perf_counter()
     selector.warm_up(None, seconds=1.0)
     ws_f = torch.empty(boba.load().boba_graph_features_workspace(), dtype=torch.uint8, device=dev)
+    lead = torch.empty(1 << 16, dtype=torch.float32, device=dev)
     X = np.zeros((len(specs), selector.N_FEAT), np.float32)
     rows = []
     for i, (sp, (src_h, dst_h)) in enumerate(zip(specs, graphs)):
@@ -823,23 +824,19 @@ def bench_selector(sel_data):
         dst = torch.from_numpy(dst_h).to(dev)
         val = torch.from_numpy(graphgen.uniform_values(src_h.size, sp.seed + 3)).to(dev)
         x = torch.from_numpy(graphgen.uniform_values(sp.n, sp.seed + 4)).to(dev)
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-        e[0].record()
-        f = boba.boba_graph_features(src, dst, sp.n, ws=ws_f)
-        e[1].record()
-        torch.cuda.synchronize()
+        f, t_feat = selector.time_features(src, dst, sp.n, ws_f, lead)
         X[i] = f.cpu().numpy()
         med = selector.measure_paths(src, dst, val, x, sp.n, reps=3)
-        med["t_feat"] = e[0].elapsed_time(e[1])
+        med["t_feat"] = t_feat
         med.update({"kind": sp.kind, "n": sp.n, "m": int(src_h.size)})
         rows.append(med)
     t_inf = selector.time_inference(model.params)
-    res = selector.evaluate(model.params, X, rows, t_inf, model.gate)
+    res = selector.evaluate(model.params, X, rows, t_inf, model.gate, model.meta.get("gate_alone"))
     res.update({"t_infer_ms": t_inf, "seconds": time.perf_counter() - t0,
                 "graphs_desc": "the first held-out graphs of the selector's training run (regular and large, "
                                "10:1), each path the median of 3 timings after a warm-up round"})
-    log(f"selector: {res['selector_vs_oracle']:.3f} of the oracle choice (gate only "
-        f"{res['gate_only_vs_oracle']:.3f}, network only {res['ungated_selector_vs_oracle']:.3f}, "
+    log(f"selector: {res['selector_vs_oracle']:.3f} of the oracle choice (gate alone "
+        f"{res['gate_alone_vs_oracle']:.3f}, network only {res['ungated_selector_vs_oracle']:.3f}, "
         f"never {res['never_vs_oracle']:.3f}, always {res['always_vs_oracle']:.3f}) in {res['seconds']:.1f}s")
     return res
 

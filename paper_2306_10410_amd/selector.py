@@ -148,6 +148,29 @@ def warm_up(log=None, seconds=2.0):
         log(f"warm-up {time.perf_counter() - t0:.1f}s")
 
 
+def time_features(src, dst, n, ws, lead, reps=3):
+    """The features of a graph and their cost, timed like the two paths: a
+    warm-up call, then the median of `reps` calls, each after an untimed
+    lead-in (the first touch of a new graph -- TLB and cache misses -- is paid
+    by whatever runs first on it, whichever policy is used)."""
+    import torch
+
+    from . import boba
+
+    f = boba.boba_graph_features(src, dst, n, ws=ws)
+    ts = []
+    for _ in range(reps):
+        e = _events(torch, 2)
+        for _ in range(4):
+            lead.fill_(0.0)
+        e[0].record()
+        boba.boba_graph_features(src, dst, n, out=f, ws=ws)
+        e[1].record()
+        torch.cuda.synchronize()
+        ts.append(e[0].elapsed_time(e[1]))
+    return f, float(np.median(ts))
+
+
 def build_dataset(specs, *, reps=5, log=None, pool=None):
     """Features (GPU kernel), both path timings and the label for every spec.
     Graphs come from `pool` (see start_pool) when given."""
@@ -159,21 +182,17 @@ def build_dataset(specs, *, reps=5, log=None, pool=None):
     X = np.zeros((len(specs), N_FEAT), np.float32)
     rows = []
     ws_f = torch.empty(boba.load().boba_graph_features_workspace(), dtype=torch.uint8, device=dev)
+    lead = torch.empty(1 << 16, dtype=torch.float32, device=dev)
     graphs = pool.map(_gen, specs, chunksize=4) if pool is not None else map(_gen, specs)
     for i, (s, (src_h, dst_h)) in enumerate(zip(specs, graphs)):
         src = torch.from_numpy(src_h).to(dev)
         dst = torch.from_numpy(dst_h).to(dev)
         val = torch.from_numpy(graphgen.uniform_values(src_h.size, s.seed + 3)).to(dev)
         x = torch.from_numpy(graphgen.uniform_values(s.n, s.seed + 4)).to(dev)
-        # feature + inference overhead as served
-        e = _events(torch, 2)
-        e[0].record()
-        f = boba.boba_graph_features(src, dst, s.n, ws=ws_f)
-        e[1].record()
-        torch.cuda.synchronize()
+        f, t_feat = time_features(src, dst, s.n, ws_f, lead)
         X[i] = f.cpu().numpy()
         med = measure_paths(src, dst, val, x, s.n, reps=reps)
-        med["t_feat"] = e[0].elapsed_time(e[1])
+        med["t_feat"] = t_feat
         med.update({"kind": s.kind, "n": s.n, "m": int(src_h.size), "seed": s.seed})
         rows.append(med)
         if log and (i + 1) % 250 == 0:
@@ -268,9 +287,10 @@ class Model:
     (log2(1 + m) below which the graph is not reordered and no feature is
     computed)."""
 
-    def __init__(self, params, gate=float("-inf")):
+    def __init__(self, params, gate=float("-inf"), meta=None):
         self.params = np.asarray(params, np.float32)
         self.gate = float(gate)
+        self.meta = dict(meta or {})
 
 
 def save_model(path, params, mu, sigma, meta=None, gate=float("-inf")):
@@ -291,7 +311,13 @@ def load_model(path):
               and gate.shape == (1,) and not np.isnan(gate[0])
               and bytes(z["checksum"]).decode() == _digest([params, mu, sigma, gate])
               and np.all(np.isfinite(params)))
-        return Model(params, gate[0]) if ok else None
+        if not ok:
+            return None
+        try:
+            meta = json.loads(bytes(z["meta"]).decode()) if "meta" in z.files else {}
+        except ValueError:
+            meta = {}
+        return Model(params, gate[0], meta if isinstance(meta, dict) else {})
     except Exception:
         return None
 
@@ -356,10 +382,22 @@ def choose_gate(pred, rows, t_infer_ms):
     return float(best)
 
 
-def evaluate(params, X, rows, t_infer_ms, gate=float("-inf")):
+def best_gate_alone(rows):
+    """The threshold that minimises the total time of the gate alone (below
+    it keep the order, above it always reorder; no features) on the given
+    (training) graphs."""
+    never = np.array([r["never"] for r in rows])
+    always = np.array([r["always"] for r in rows])
+    lm = np.log2(1.0 + np.array([r["m"] for r in rows], np.float64))
+    cands = np.concatenate([[-np.inf], np.unique(lm), [np.inf]])
+    return float(min(cands, key=lambda g: float(np.where(lm >= g, always, never).sum())))
+
+
+def evaluate(params, X, rows, t_infer_ms, gate=float("-inf"), gate_alone=None):
     """Held-out totals: the selector's choice (plus its feature and inference
-    time above the gate) against the oracle choice, always-reorder and
-    never-reorder."""
+    time above the gate) against the oracle choice, always-reorder,
+    never-reorder, the gate alone at the selector's threshold and (if given)
+    the gate alone at its own best threshold on the training graphs."""
     import torch
 
     from . import boba
@@ -375,12 +413,16 @@ def evaluate(params, X, rows, t_infer_ms, gate=float("-inf")):
     lm = np.log2(1.0 + np.array([r["m"] for r in rows], np.float64))
     above = lm >= gate
     t_gate = np.where(above, always, never)
+    ga = gate if gate_alone is None else float(gate_alone)
+    t_alone = np.where(lm >= ga, always, never)
     opt = np.minimum(never, always)
     sel_total = float(t_sel.sum())
     truth = always < never
     return {"graphs": len(rows), "gate_log2m": gate, "selector_ms": sel_total,
             "oracle_choice_ms": float(opt.sum()), "always_ms": float(always.sum()), "never_ms": float(never.sum()),
             "gate_only_ms": float(t_gate.sum()), "mlp_only_ms": float(t_nogate.sum()),
+            "gate_alone_log2m": ga, "gate_alone_ms": float(t_alone.sum()),
+            "gate_alone_vs_oracle": float(t_alone.sum()) / float(opt.sum()),
             "selector_vs_oracle": sel_total / float(opt.sum()),
             "selector_vs_always": sel_total / float(always.sum()),
             "selector_vs_never": sel_total / float(never.sum()),
@@ -467,7 +509,7 @@ def main(argv=None):
         if pool is not None:
             pool.shutdown()
         t_inf = time_inference(model.params)
-        res = evaluate(model.params, Xho, rho, t_inf, model.gate)
+        res = evaluate(model.params, Xho, rho, t_inf, model.gate, model.meta.get("gate_alone"))
         res.update({"model": args.eval_model, "t_infer_ms": t_inf,
                     "t_feat_ms_median": float(np.median([r["t_feat"] for r in rho]))})
         print(json.dumps(res), flush=True)
@@ -512,11 +554,12 @@ def train_and_report(args, log, Xtr, ytr, rtr, Xho, yho, rho):
     from . import boba
     pred_tr = boba.boba_mlp_forward(torch.from_numpy(params).cuda(), torch.from_numpy(Xtr).cuda()).cpu().numpy()
     gate = choose_gate(pred_tr, rtr, t_inf)
-    log(f"size gate: log2(1 + m) >= {gate:.3f}")
+    alone = best_gate_alone(rtr)
+    log(f"size gate: log2(1 + m) >= {gate:.3f} (the gate alone would take {alone:.3f})")
     os.makedirs(os.path.dirname(args.out) or ".", exist_ok=True)
     save_model(args.out, params, mu, sigma, {"train": len(rtr), "epochs": args.epochs,
-                                             "weighted": bool(args.weighted)}, gate=gate)
-    res = evaluate(params, Xho, rho, t_inf, gate)
+                                             "weighted": bool(args.weighted), "gate_alone": alone}, gate=gate)
+    res = evaluate(params, Xho, rho, t_inf, gate, alone)
     res.update({"train_graphs": len(rtr), "train_mse": hist[-1], "t_infer_ms": t_inf, "weighted": bool(args.weighted),
                 "t_feat_ms_median": float(np.median([r["t_feat"] for r in rho]))})
     print(json.dumps(res), flush=True)
