@@ -130,7 +130,7 @@ BOBA_API boba_status boba_relabel(const int32_t *src, const int32_t *dst, int64_
  * slice is held on chip while its records get their new IDs, and the IDs go
  * back to edge order.  Same results as boba_relabel; faster on large graphs
  * (RMAT scale 24: 3.3 ms instead of 7.6 ms).  Graphs of more than 2^25
- * vertices or src/dst not 16-byte aligned take boba_relabel's path.
+ * vertices take boba_relabel's path.
  *   ws  at least boba_relabel_bucketed_workspace(n, m) bytes, 256-byte aligned
  *       (about 16 bytes per edge).
  * Errors: as boba_relabel, and BOBA_ERR_WORKSPACE. */
@@ -141,9 +141,9 @@ BOBA_API boba_status boba_relabel_bucketed(const int32_t *src, const int32_t *ds
 
 /* ------------------------------------------------- reorder + relabel ---
  * boba_reorder followed by boba_relabel in one call (same results as the two
- * calls).  For graphs up to 2^25 vertices with 16-byte aligned src/dst, the
- * relabel reuses the reorder's vertex-bucketed copy of the edge list instead
- * of gathering perm[] once per endpoint.  src_out / dst_out may equal src / dst
+ * calls).  For graphs up to 2^25 vertices the relabel reuses the reorder's
+ * vertex-bucketed copy of the edge list instead of gathering perm[] once per
+ * endpoint.  src_out / dst_out may equal src / dst
  * (in place); other overlaps are not allowed.
  *   ws  at least boba_reorder_relabel_workspace(n, m) bytes, 256-byte aligned.
  * Errors: as boba_reorder. */

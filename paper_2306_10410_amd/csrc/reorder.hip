@@ -5,7 +5,7 @@
 // exact minimum), then perm[v] = the rank of key(v) = r[v] among all keys, where
 // a vertex that never occurs has key 2m + v (it follows all others in
 // increasing ID).  Two paths:
-//   bucketed (n <= 2^25, 16-byte aligned src/dst; the normal case)
+//   bucketed (n <= 2^25; the normal case)
 //     split     per tile of S, records {offset, v mod 2^15} sorted by vertex
 //               bucket (v >> 15) in LDS, written segment by segment
 //     min       per (bucket, slice): the bucket's r in LDS, every record folded
@@ -440,16 +440,18 @@ __device__ inline void long_drain(const LongQueue &q, uint32_t wave, uint32_t nw
 inline uint32_t split_region(uint32_t nb) { return (kTileT + 3 * nb + 3) & ~3u; }
 
 // Loads tile t (32 elements per thread, element k0 + j*4096 + 4*tid + q, so
-// that every load instruction is coalesced).  Past the end: -1.
+// that every load instruction is coalesced; 16-byte loads when src and dst
+// are 16-byte aligned).  Past the end: -1.
 __device__ __forceinline__ void split_load(const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
-                                           uint32_t m, uint32_t tiles_half, uint32_t t, int32_t (&v)[kSplitPer]) {
+                                           uint32_t m, uint32_t tiles_half, uint32_t t, bool vec,
+                                           int32_t (&v)[kSplitPer]) {
     const bool h = t >= tiles_half;
     const uint32_t k0 = (t - (h ? tiles_half : 0u)) * kTileT;
     const int32_t *a = h ? dst : src;
 #pragma unroll
     for (int j = 0; j < kSplitPer / 4; ++j) {
         const uint32_t e = k0 + j * (4 * kSplitThreads) + 4 * threadIdx.x;
-        if (e + 3 < m) {
+        if (vec && e + 3 < m) {
             const v4i x = __builtin_nontemporal_load((const v4i *)(a + e));
             v[4 * j] = x.x;
             v[4 * j + 1] = x.y;
@@ -468,7 +470,8 @@ __device__ __forceinline__ void split_load(const int32_t *__restrict__ src, cons
 __global__ __launch_bounds__(kSplitThreads) void k_bucket_split(const int32_t *__restrict__ src,
                                                                  const int32_t *__restrict__ dst, uint32_t m,
                                                                  uint32_t tiles_half, uint32_t n, uint32_t nb,
-                                                                 uint32_t region, uint32_t *__restrict__ recs,
+                                                                 uint32_t region, bool vec,
+                                                                 uint32_t *__restrict__ recs,
                                                                  uint32_t *__restrict__ tile_off, int32_t *flag) {
     __shared__ __align__(16) uint32_t stage[kTileT + 3 * kMaxBuckets];
     __shared__ uint32_t hist[kMaxBuckets];
@@ -480,7 +483,7 @@ __global__ __launch_bounds__(kSplitThreads) void k_bucket_split(const int32_t *_
     const uint32_t t_begin = blockIdx.x * per;
     const uint32_t t_end = min(nt, t_begin + per);
     int32_t v[kSplitPer];
-    if (t_begin < t_end) split_load(src, dst, m, tiles_half, t_begin, v);
+    if (t_begin < t_end) split_load(src, dst, m, tiles_half, t_begin, vec, v);
     bool bad = false;
     for (uint32_t t = t_begin; t < t_end; ++t) {
         const bool h = t >= tiles_half;
@@ -561,7 +564,7 @@ __global__ __launch_bounds__(kSplitThreads) void k_bucket_split(const int32_t *_
             }
         }
         __syncthreads();
-        if (t + 1 < t_end) split_load(src, dst, m, tiles_half, t + 1, v);
+        if (t + 1 < t_end) split_load(src, dst, m, tiles_half, t + 1, vec, v);
         v4u *out = (v4u *)(recs + (size_t)t * region);
         const v4u *st = (const v4u *)stage;
         for (uint32_t i = tid; i < total / 4; i += kSplitThreads) __builtin_nontemporal_store(st[i], &out[i]);
@@ -838,18 +841,21 @@ __global__ __launch_bounds__(kSplitThreads) void k_tile_unsplit(const uint32_t *
 // occurs).  perm[v] counts the vertices with a smaller key (key = r, or 2m + v
 // in the tail).  Keys below 2m are grouped into key blocks of 2^kbits
 // positions (about 4096 blocks); the isolated vertices form one extra block
-// after them.
-//   rank_count    per vertex bucket: its vertices per key block (LDS counters),
-//                 stored bucket-major
+// after them.  The ranking's vertex buckets ("rank buckets", 2^rbits vertices,
+// rbits <= kVBits) are its own: narrower than the split's when the graph has
+// few split buckets, so that these kernels still spread over the GPU.
+//   rank_count    per rank bucket: its vertices per key block (LDS counters),
+//                 stored bucket-major; with several bucket_min slices it
+//                 also writes the merged minimum back to slice 0
 //   scan          transposed to block-major, exclusive scan: where bucket b's
 //                 entries of key block k start in the entry list E (and how
 //                 many keys precede the block); transposed back for the
 //                 per-bucket kernels
-//   rank_scatter  per vertex bucket: {r, v} of every occurring vertex into E
+//   rank_scatter  per rank bucket: {r, v} of every occurring vertex into E
 //   rank_block    per key block: its keys as an LDS bitmap with prefix
 //                 popcounts; rank = keys in earlier blocks + keys before it in
 //                 the block; writes order[rank] = v and the rank beside E
-//   rank_perm     per vertex bucket: the ranks back into an LDS perm slice;
+//   rank_perm     per rank bucket: the ranks back into an LDS perm slice;
 //                 isolated vertices take the tail ranks in increasing ID
 // Every step streams or works in LDS: no device-wide random atomics.
 constexpr uint32_t kMinKeyBits = 15;
@@ -857,6 +863,10 @@ constexpr uint32_t kPermChunk = 1024;  // key blocks rank_perm takes at a time (
 constexpr uint32_t kMaxKeyBits = 18;                            // rank_block LDS <= 48 KB
 constexpr uint32_t kTargetKeyBlocks = 4096;                    // bounds a key block's entries
 constexpr uint32_t kMaxKeyBlocks = 1u << (32 - kMaxKeyBits);    // 2m < 2^32
+constexpr uint32_t kMinRankBits = 10;                           // a rank bucket spans at least kMinThreads vertices
+constexpr uint64_t kTargetRankBuckets = 512;
+constexpr uint64_t kMaxRankTable = 1u << 21;
+static_assert((1u << kMinRankBits) == (uint32_t)kMinThreads, "rank_perm's flag words assume it");
 
 __device__ __forceinline__ uint32_t merged_r(const uint32_t *__restrict__ rpart, uint32_t slices, uint32_t n,
                                              uint32_t v) {
@@ -867,20 +877,23 @@ __device__ __forceinline__ uint32_t merged_r(const uint32_t *__restrict__ rpart,
 
 // cnt_b[b][k]: bucket-major (coalesced rows); cnt gets its final zero, where
 // the scan of the transposed counts leaves the total.
-__global__ __launch_bounds__(kMinThreads) void k_rank_count(const uint32_t *__restrict__ rpart, uint32_t slices,
-                                                            uint32_t n, uint32_t nb, uint32_t nblk, uint32_t kbits,
-                                                            uint32_t *__restrict__ cnt_b, uint32_t *__restrict__ cnt) {
+__global__ __launch_bounds__(kMinThreads) void k_rank_count(uint32_t *__restrict__ rpart, uint32_t slices,
+                                                            uint32_t n, uint32_t nb, uint32_t rbits, uint32_t nblk,
+                                                            uint32_t kbits, uint32_t *__restrict__ cnt_b,
+                                                            uint32_t *__restrict__ cnt) {
     __shared__ uint32_t h[kMaxKeyBlocks + 1];
     const uint32_t b = blockIdx.x;
-    const uint32_t v0 = b * kBucketW;
-    const uint32_t cntv = min(kBucketW, n - v0);
+    const uint32_t w = 1u << rbits;
+    const uint32_t v0 = b << rbits;
+    const uint32_t cntv = min(w, n - v0);
     const uint32_t lane = threadIdx.x & (kWave - 1);
     for (uint32_t k = threadIdx.x; k <= nblk; k += kMinThreads) h[k] = 0;
     if (b == 0 && threadIdx.x == 0) cnt[(size_t)(nblk + 1) * nb] = 0;  // the scan's total lands here
     __syncthreads();
-    for (uint32_t q = 0; q < kBucketW; q += kMinThreads) {
+    for (uint32_t q = 0; q < cntv; q += kMinThreads) {
         const uint32_t i = q + threadIdx.x;
         const uint32_t p = i < cntv ? merged_r(rpart, slices, n, v0 + i) : 0u;
+        if (slices > 1 && i < cntv) rpart[v0 + i] = p;  // each vertex is read and written by this thread only
         const bool iso = i < cntv && p == kInf;
         // isolated vertices are common (about 38% in RMAT): one atomic per wave
         const uint64_t bal = __ballot(iso);
@@ -891,13 +904,14 @@ __global__ __launch_bounds__(kMinThreads) void k_rank_count(const uint32_t *__re
     for (uint32_t k = threadIdx.x; k <= nblk; k += kMinThreads) cnt_b[(size_t)b * (nblk + 1) + k] = h[k];
 }
 
-__global__ __launch_bounds__(kMinThreads) void k_rank_scatter(const uint32_t *__restrict__ rpart, uint32_t slices,
-                                                              uint32_t n, uint32_t nblk, uint32_t kbits,
+// r: the merged minima (slice 0 after rank_count)
+__global__ __launch_bounds__(kMinThreads) void k_rank_scatter(const uint32_t *__restrict__ r, uint32_t n,
+                                                              uint32_t rbits, uint32_t nblk, uint32_t kbits,
                                                               const uint32_t *__restrict__ off_b, uint2 *__restrict__ E) {
     __shared__ uint32_t cur[kMaxKeyBlocks];
     const uint32_t b = blockIdx.x;
-    const uint32_t v0 = b * kBucketW;
-    const uint32_t cntv = min(kBucketW, n - v0);
+    const uint32_t v0 = b << rbits;
+    const uint32_t cntv = min(1u << rbits, n - v0);
     for (uint32_t k = threadIdx.x; k < nblk; k += kMinThreads) cur[k] = off_b[(size_t)b * (nblk + 1) + k];
     __syncthreads();
     constexpr int U = 8;
@@ -906,7 +920,7 @@ __global__ __launch_bounds__(kMinThreads) void k_rank_scatter(const uint32_t *__
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint32_t i = i0 + u * kMinThreads;
-            p[u] = i < cntv ? merged_r(rpart, slices, n, v0 + i) : kInf;
+            p[u] = i < cntv ? r[v0 + i] : kInf;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -1026,7 +1040,7 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_block(uint2 *__restrict__
     }
 }
 
-// Per vertex bucket: the ranks of its occurring vertices come back from the
+// Per rank bucket: the ranks of its occurring vertices come back from the
 // entry list into an LDS perm slice (segment bounds 64 at a time, the first 64
 // entries of 8 segments in flight); isolated vertices (still unset) take the
 // tail ranks from iso_base on in increasing ID, via one ballot bitmap and one
@@ -1034,7 +1048,7 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_block(uint2 *__restrict__
 __global__ __launch_bounds__(kMinThreads) void k_rank_perm(const uint2 *__restrict__ E,
                                                            const uint32_t *__restrict__ off_b,
                                                            const uint32_t *__restrict__ cnt_b, uint32_t nblk,
-                                                           uint32_t n, int32_t *__restrict__ perm,
+                                                           uint32_t n, uint32_t rbits, int32_t *__restrict__ perm,
                                                            int32_t *__restrict__ order) {
     __shared__ uint32_t lp[kBucketW];
     __shared__ uint32_t pre[kPermChunk + 1];  // entries of the bucket in earlier key blocks of the chunk
@@ -1044,11 +1058,12 @@ __global__ __launch_bounds__(kMinThreads) void k_rank_perm(const uint2 *__restri
     // neighbouring buckets on one XCD: their slices of a key block lie side by
     // side in E and are read through the same L2 (0.12 -> 0.106 ms at RMAT-24)
     const uint32_t b = xcd_work_index(blockIdx.x, gridDim.x);
-    const uint32_t v0 = b * kBucketW;
-    const uint32_t cntv = min(kBucketW, n - v0);
+    const uint32_t w = 1u << rbits;  // kMinThreads .. kBucketW vertices
+    const uint32_t v0 = b << rbits;
+    const uint32_t cntv = min(w, n - v0);
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = threadIdx.x / kWave;
-    for (uint32_t i = threadIdx.x; i < kBucketW; i += kMinThreads) lp[i] = kInf;
+    for (uint32_t i = threadIdx.x; i < w; i += kMinThreads) lp[i] = kInf;
     const uint32_t *ob = off_b + (size_t)b * (nblk + 1);
     const uint32_t *cb = cnt_b + (size_t)b * (nblk + 1);
     // The bucket's entries lie in one small slice per key block.  Per chunk of
@@ -1089,13 +1104,13 @@ __global__ __launch_bounds__(kMinThreads) void k_rank_perm(const uint2 *__restri
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    if (x[u].y != kInf) lp[(x[u].y - v0) & (kBucketW - 1)] = x[u].x;
+                    if (x[u].y != kInf) lp[(x[u].y - v0) & (w - 1)] = x[u].x;
             }
         }
         __syncthreads();  // pre and obs are rewritten by the next chunk
     }
     // isolated flags: vertices [u*1024 + wave*64, +64) -> words 32u + 2 wave, +1
-    for (uint32_t u = 0; u < kBucketW / kMinThreads; ++u) {
+    for (uint32_t u = 0; u < w / kMinThreads; ++u) {
         const uint32_t i = u * kMinThreads + threadIdx.x;
         const uint64_t bal = __ballot(i < cntv && lp[i] == kInf);
         if (lane == 0) {
@@ -1105,7 +1120,7 @@ __global__ __launch_bounds__(kMinThreads) void k_rank_perm(const uint2 *__restri
         }
     }
     __syncthreads();
-    const uint32_t word = flags[threadIdx.x];  // vertices 32 t .. 32 t + 31
+    const uint32_t word = threadIdx.x < w / 32 ? flags[threadIdx.x] : 0u;  // vertices 32 t .. 32 t + 31
     uint32_t tot;
     const uint32_t before = block_exclusive_scan<kMinThreads>(__popc(word), OpSum{}, scan_lds, tot);
     uint32_t left = word, k = ob[nblk] + before;
@@ -1128,6 +1143,7 @@ struct ReorderPlan {
     bool bucketed;
     uint32_t nb, tiles_half, nt, region, slices, tps;
     uint32_t kbits, nblk;  // key blocks of the bucketed ranking
+    uint32_t rbits, nbr;   // rank buckets: 2^rbits vertices each, nbr of them
 };
 
 ReorderPlan reorder_plan(int64_t n, int64_t m) {
@@ -1157,6 +1173,15 @@ ReorderPlan reorder_plan(int64_t n, int64_t m) {
         P.kbits = kMinKeyBits;
         while (P.kbits < kMaxKeyBits && (keys >> P.kbits) > kTargetKeyBlocks) ++P.kbits;
         P.nblk = (uint32_t)((keys + (1ull << P.kbits) - 1) >> P.kbits);
+        // rank buckets: narrower than the split's until there are about 512
+        // (two 1024-thread workgroups per CU), while the count table
+        // (key blocks + 1) x rank buckets stays within 2^21 words
+        P.rbits = kVBits;
+        auto nbr_at = [&](uint32_t bits) { return ceil_div((uint64_t)n, 1ull << bits); };
+        while (P.rbits > kMinRankBits && nbr_at(P.rbits) < kTargetRankBuckets &&
+               (uint64_t)(P.nblk + 1) * nbr_at(P.rbits - 1) <= kMaxRankTable)
+            --P.rbits;
+        P.nbr = (uint32_t)nbr_at(P.rbits);
     }
     P.tps = P.nt ? ceil_div(P.nt, P.slices) : 0;
     return P;
@@ -1187,7 +1212,7 @@ ReorderLayout reorder_layout(void *ws, int64_t n, int64_t m, const ReorderPlan &
     L.tile_off = c.take<uint32_t>(P.bucketed ? (size_t)P.nt * (P.nb + 1) : 0);
     L.off_t = c.take<uint32_t>(P.bucketed ? (size_t)P.nt * (P.nb + 1) : 0);
     L.vals = c.take<uint32_t>(P.bucketed && with_vals ? (size_t)P.nt * P.region : 0);
-    L.ncnt = P.bucketed ? (P.nblk + 1) * P.nb + 1 : 0;
+    L.ncnt = P.bucketed ? (P.nblk + 1) * P.nbr + 1 : 0;
     L.cnt = c.take<uint32_t>(L.ncnt);
     L.cnt_b = c.take<uint32_t>(P.bucketed ? L.ncnt - 1 : 0);
     L.off_b = c.take<uint32_t>(P.bucketed ? L.ncnt - 1 : 0);
@@ -1239,13 +1264,13 @@ boba_status reorder_run(const int32_t *src, const int32_t *dst, uint32_t um, uin
                         dst, um, un, L.W, L.nw, perm, order, so, dso, flag);
         return BOBA_OK;
     }
-    const bool bucketed = P.bucketed && aligned16(src) && aligned16(dst);
+    const bool bucketed = P.bucketed;
     *path = bucketed ? PATH_BUCKETED : PATH_DIRECT;
     const uint32_t tail = 2 * um;
     if (bucketed) {
         BOBA_LAUNCH("bucket_split", k_bucket_split, dim3(P.nt < device_cus() ? P.nt : device_cus()),
                     dim3(kSplitThreads), stream, src, dst, um,
-                    P.tiles_half, un, P.nb, P.region, L.recs, L.tile_off, flag);
+                    P.tiles_half, un, P.nb, P.region, aligned16(src) && aligned16(dst), L.recs, L.tile_off, flag);
         BOBA_LAUNCH("bucket_transpose", k_transpose, dim3(ceil_div(P.nb + 1, 32), ceil_div(P.nt, 32)), dim3(256),
                     stream, (const uint32_t *)L.tile_off, P.nt, P.nb + 1, L.off_t);
         if (racy)
@@ -1257,28 +1282,28 @@ boba_status reorder_run(const int32_t *src, const int32_t *dst, uint32_t um, uin
                         (const uint32_t *)L.recs, (const uint32_t *)L.off_t, P.nt, P.tiles_half, P.region, P.nb,
                         P.tps, min_batch(P), un, inter ? 1u : um, inter ? 2u : 1u, L.r);
         const uint32_t kcols = P.nblk + 1;  // key blocks and the tail block
-        BOBA_LAUNCH("rank_count", k_rank_count, dim3(P.nb), dim3(kMinThreads), stream, (const uint32_t *)L.r,
-                    P.slices, un, P.nb, P.nblk, P.kbits, L.cnt_b, L.cnt);
+        BOBA_LAUNCH("rank_count", k_rank_count, dim3(P.nbr), dim3(kMinThreads), stream, L.r, P.slices, un, P.nbr,
+                    P.rbits, P.nblk, P.kbits, L.cnt_b, L.cnt);
         // bucket-major counts -> block-major, scanned in place -> bucket-major offsets
-        BOBA_LAUNCH("rank_transpose", k_transpose, dim3(ceil_div(kcols, 32), ceil_div(P.nb, 32)), dim3(256), stream,
-                    (const uint32_t *)L.cnt_b, P.nb, kcols, L.cnt);
+        BOBA_LAUNCH("rank_transpose", k_transpose, dim3(ceil_div(kcols, 32), ceil_div(P.nbr, 32)), dim3(256), stream,
+                    (const uint32_t *)L.cnt_b, P.nbr, kcols, L.cnt);
         if (boba_status e = device_scan<OpSum, false>("rank_scan", LoadArr{L.cnt}, StoreArr{L.cnt}, L.ncnt,
                                                       L.cnt_partial, stream))
             return e;
-        BOBA_LAUNCH("rank_transpose", k_transpose, dim3(ceil_div(P.nb, 32), ceil_div(kcols, 32)), dim3(256), stream,
-                    (const uint32_t *)L.cnt, kcols, P.nb, L.off_b);
-        BOBA_LAUNCH("rank_scatter", k_rank_scatter, dim3(P.nb), dim3(kMinThreads), stream, (const uint32_t *)L.r,
-                    P.slices, un, P.nblk, P.kbits, (const uint32_t *)L.off_b, L.E);
+        BOBA_LAUNCH("rank_transpose", k_transpose, dim3(ceil_div(P.nbr, 32), ceil_div(kcols, 32)), dim3(256), stream,
+                    (const uint32_t *)L.cnt, kcols, P.nbr, L.off_b);
+        BOBA_LAUNCH("rank_scatter", k_rank_scatter, dim3(P.nbr), dim3(kMinThreads), stream, (const uint32_t *)L.r,
+                    un, P.rbits, P.nblk, P.kbits, (const uint32_t *)L.off_b, L.E);
         {
             const size_t lds = rank_block_lds(P.kbits);
             const int tok = timing_begin("rank_block", stream);
             hipLaunchKernelGGL(k_rank_block, dim3(P.nblk), dim3(kRankThreads), lds, stream, L.E,
-                               (const uint32_t *)L.cnt, P.nb, P.kbits, order);
+                               (const uint32_t *)L.cnt, P.nbr, P.kbits, order);
             timing_end(tok, stream);
             if (boba_status e = check_launch("rank_block")) return e;
         }
-        BOBA_LAUNCH("rank_perm", k_rank_perm, dim3(P.nb), dim3(kMinThreads), stream, (const uint2 *)L.E,
-                    (const uint32_t *)L.off_b, (const uint32_t *)L.cnt_b, P.nblk, un, perm, order);
+        BOBA_LAUNCH("rank_perm", k_rank_perm, dim3(P.nbr), dim3(kMinThreads), stream, (const uint2 *)L.E,
+                    (const uint32_t *)L.off_b, (const uint32_t *)L.cnt_b, P.nblk, un, P.rbits, perm, order);
         return BOBA_OK;
     } else {
         BOBA_LAUNCH("reorder_init", k_reorder_init, dim3(grid_for(un > L.nw ? un : L.nw, kBlock * 4)),
@@ -1534,11 +1559,11 @@ extern "C" boba_status boba_relabel_bucketed(const int32_t *src, const int32_t *
     if (!flag) return BOBA_ERR_HIP;
     const uint32_t um = (uint32_t)m, un = (uint32_t)n;
     const ReorderPlan P = reorder_plan(n, m);
-    if (!P.bucketed || !aligned16(src) || !aligned16(dst))
-        return relabel_run(src, dst, um, perm, un, src_out, dst_out, flag, stream);
+    if (!P.bucketed) return relabel_run(src, dst, um, perm, un, src_out, dst_out, flag, stream);
     const RelabelLayout L = relabel_layout(ws, P);
     BOBA_LAUNCH("bucket_split", k_bucket_split, dim3(P.nt < device_cus() ? P.nt : device_cus()), dim3(kSplitThreads),
-                stream, src, dst, um, P.tiles_half, un, P.nb, P.region, L.recs, L.tile_off, flag);
+                stream, src, dst, um, P.tiles_half, un, P.nb, P.region, aligned16(src) && aligned16(dst), L.recs,
+                L.tile_off, flag);
     BOBA_LAUNCH("bucket_transpose", k_transpose, dim3(ceil_div(P.nb + 1, 32), ceil_div(P.nt, 32)), dim3(256), stream,
                 (const uint32_t *)L.tile_off, P.nt, P.nb + 1, L.off_t);
     BOBA_LAUNCH("bucket_relabel", k_bucket_relabel, dim3(P.nb * P.slices), dim3(kMinThreads), stream,

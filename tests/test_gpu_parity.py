@@ -112,7 +112,8 @@ def test_one_launch_path_limits(n, m):
 
 
 @pytest.mark.parametrize("general", [False, True])
-def test_unaligned_inputs_take_the_scalar_path(general):
+def test_unaligned_inputs(general):
+    # src/dst not 16-byte aligned: the split loads element by element
     g = graphgen.small_workload("rmat", 4096, 40001, 77)
     big_s = dev(np.concatenate([[0], g.src]).astype(np.int32))
     big_d = dev(np.concatenate([[0], g.dst]).astype(np.int32))
@@ -291,7 +292,7 @@ def test_fused_reorder_relabel_in_place_and_unaligned(general):
     out_d = torch.empty(g.m + 1, dtype=torch.int32, device="cuda")[1:]
     boba.boba_reorder_relabel(s, d, g.n, src_out=out_s, dst_out=out_d, flags=fl)
     assert np.array_equal(host(out_s), s_ref) and np.array_equal(host(out_d), d_ref)
-    # unaligned inputs: direct path
+    # unaligned inputs: the split loads element by element
     big_s = dev(np.concatenate([[0], g.src]).astype(np.int32))[1:]
     big_d = dev(np.concatenate([[0], g.dst]).astype(np.int32))[1:]
     perm, _, so, do = boba.boba_reorder_relabel(big_s, big_d, g.n, flags=fl)
@@ -318,6 +319,34 @@ def test_key_block_widths(n, m):
     perm, order = boba.boba_reorder(dev(src), dev(dst), n, flags=boba.BOBA_FLAG_INTERLEAVED)
     p_ref, o_ref = oracle.boba(src, dst, n, interleaved=True)
     assert np.array_equal(host(perm), p_ref) and np.array_equal(host(order), o_ref)
+
+
+# The ranking's vertex buckets narrow (2^15 down to 2^10 vertices) until there
+# are about 512 of them; graphs with few split buckets also fold their first
+# positions in many bucket_min slices, merged by the ranking.  Per case: the
+# rank bucket width and the slice count the plan picks.
+@pytest.mark.parametrize("kind,n,m", [
+    ("rmat", 40000, 300001),         # 2^10-vertex rank buckets, 20 slices, ragged last bucket
+    ("rmat", 33000, 2000000),        # 2^10, 124 slices
+    ("rmat", 200000, 4000000),       # 2^10, 37 slices
+    ("uniform", 3000000, 20000000),  # 2^12, 3 slices
+])
+def test_rank_bucket_widths(kind, n, m):
+    g = graphgen.small_workload(kind, n, m, 130 + m % 11)
+    for inter in (False, True):
+        fl = boba.BOBA_FLAG_INTERLEAVED if inter else 0
+        perm, order = boba.boba_reorder(dev(g.src), dev(g.dst), n, flags=fl)
+        p_ref, o_ref = oracle.boba(g.src, g.dst, n, interleaved=inter)
+        assert np.array_equal(host(perm), p_ref) and np.array_equal(host(order), o_ref), f"interleaved={inter}"
+    # views one int32 into larger arrays: the split's element-wise loads
+    big_s = dev(np.concatenate([[0], g.src]).astype(np.int32))[1:]
+    big_d = dev(np.concatenate([[0], g.dst]).astype(np.int32))[1:]
+    fp, fo, fs, fd = boba.boba_reorder_relabel(big_s, big_d, n)
+    p_ref, o_ref = oracle.boba(g.src, g.dst, n)
+    s_ref, d_ref = oracle.relabel(g.src, g.dst, p_ref)
+    assert np.array_equal(host(fp), p_ref) and np.array_equal(host(fo), o_ref)
+    assert np.array_equal(host(fs), s_ref) and np.array_equal(host(fd), d_ref)
+    assert boba.boba_check_device_error() == boba.BOBA_OK
 
 
 def test_mostly_isolated_and_hub_graphs():
@@ -446,7 +475,7 @@ def test_bucketed_relabel_matches_the_gather(n, m):
     s_ref, d_ref = oracle.relabel(src, dst, perm)
     s2, d2 = boba.boba_relabel_bucketed(dev(src), dev(dst), dev(perm))
     assert np.array_equal(host(s2), s_ref) and np.array_equal(host(d2), d_ref)
-    # in place, and unaligned views (the gather path)
+    # in place, and unaligned views (element-wise loads in the split)
     s_d, d_d = dev(src), dev(dst)
     boba.boba_relabel_bucketed(s_d, d_d, dev(perm), src_out=s_d, dst_out=d_d)
     assert np.array_equal(host(s_d), s_ref) and np.array_equal(host(d_d), d_ref)

@@ -1,8 +1,8 @@
 """boba_reorder_noalloc, the reorder for callers that cannot allocate, against
 boba_reorder (the entry point with a caller workspace) through the C ABI:
 bit-identical perm and order on consecutive calls that share the library's
-static scratch, the second on a smaller graph, and on the direct
-(unaligned-input) path.  Both are also checked against the CPU oracle."""
+static scratch, the second on a smaller graph, and on unaligned inputs
+(element-wise loads in the split).  Both are also checked against the CPU oracle."""
 import numpy as np
 import pytest
 import torch
@@ -17,7 +17,7 @@ pytestmark = [pytest.mark.gpu, requires_gpu]
 def both(g, flags=0, shift=0):
     """perm/order from boba_reorder and from boba_reorder_noalloc on the same
     device arrays; shift > 0 starts src/dst that many int32 into their buffers
-    (not 16-byte aligned: the direct scatter path)."""
+    (not 16-byte aligned: the split loads element by element)."""
     s_buf = dev(np.concatenate([np.zeros(shift, np.int32), g.src]))
     d_buf = dev(np.concatenate([np.zeros(shift, np.int32), g.dst]))
     s, d = s_buf[shift:], d_buf[shift:]
@@ -47,7 +47,7 @@ def test_two_calls_in_a_row_second_smaller():
     check(small)
 
 
-def test_interleaved_and_direct_path():
+def test_interleaved_and_unaligned():
     g = graphgen.small_workload("rgg", 20000, 150000, 73)
     check(g, flags=boba.BOBA_FLAG_INTERLEAVED)
     check(g, shift=1)
