@@ -209,7 +209,9 @@ BOBA_API boba_status spmv_csr(const int32_t *rowptr, const int32_t *col, const f
  * be < 2^31; each graph must satisfy boba_reorder's limits. */
 typedef struct boba_tuning {
     int32_t small_max_n;  /* graphs with n_g <= this run whole in one workgroup (max 32768) */
-    int32_t scatter_tile; /* positions per scatter item of a large graph (default 262144) */
+    int32_t scatter_tile; /* records per (vertex bucket, slice) item of a large graph, at
+                             most 4 slices per bucket; positions per item when large
+                             graphs scatter with atomics (default 262144) */
     int32_t vertex_tile;  /* vertices per mark / rank item (default 65536) */
     int32_t relabel_tile; /* edges per relabel item (default 262144) */
     int32_t queues;       /* 1..8 ticket queues the graphs are dealt to (default 8, one per
@@ -218,6 +220,10 @@ typedef struct boba_tuning {
     int32_t spin_limit;   /* sleeps before a wait for another workgroup gives up
                              (default 2^22, about 0.4 s); a give-up is reported as
                              BOBA_ERR_TIMEOUT by boba_check_device_error */
+    int32_t scatter_atomic; /* 1: large graphs find first positions by device-wide atomic
+                               minima instead of vertex buckets in LDS (the path graphs
+                               of more than 2^26 vertices always take); default 0.
+                               Never changes results. */
 } boba_tuning;
 typedef struct boba_batch_plan boba_batch_plan;
 BOBA_API size_t boba_batch_workspace(int32_t G, const int64_t *h_edge_off, const int64_t *h_vert_off,

@@ -345,7 +345,8 @@ class boba_tuning(ctypes.Structure):
     """Mirror of struct boba_tuning (0 = library default)."""
     _fields_ = [("small_max_n", ctypes.c_int32), ("scatter_tile", ctypes.c_int32),
                 ("vertex_tile", ctypes.c_int32), ("relabel_tile", ctypes.c_int32),
-                ("queues", ctypes.c_int32), ("spin_limit", ctypes.c_int32)]
+                ("queues", ctypes.c_int32), ("spin_limit", ctypes.c_int32),
+                ("scatter_atomic", ctypes.c_int32)]
 
 
 def _host_i64(a):

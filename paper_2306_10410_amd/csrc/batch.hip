@@ -12,9 +12,18 @@
 //   SMALL    a whole graph with n_g <= small_max_n in one workgroup: first
 //            positions by LDS atomic min, ranks through a bitmap in the graph's
 //            workspace (L2-resident), relabel by LDS gathers.
-//   SCATTER  a tile of positions of a large graph: global atomic min into the
-//            graph's r (at most 1 MB, L2-resident).
-//   MARK     a tile of vertices: set the bitmap bit of each key.
+//   SPLIT    a tile of 16384 positions of a large graph: records {offset in
+//            tile, v mod 2^15} sorted by vertex bucket (v >> 15) in LDS and
+//            written with the tile's segment offsets (as boba_reorder's split).
+//   FOLD     (vertex bucket, slice of tiles): the bucket's r in LDS, every
+//            record of its segments folded in with an LDS minimum; the
+//            slice's minima written out.
+//   SCATTER  (graphs of more than 2^26 vertices, or when asked for) a tile of
+//            positions: global atomic min into the graph's r.  Contended
+//            device-wide atomics made this several times slower than
+//            SPLIT + FOLD on the batch workloads.
+//   MARK     a tile of vertices: r = minimum over the FOLD slices, then set
+//            the bitmap bit of each key.
 //   SCAN     the graph's bitmap prefix popcounts, one workgroup.
 //   RANK     a tile of vertices: perm (and order).
 //   RELABEL  a tile of edges: src_out = perm[src], dst_out = perm[dst].
@@ -40,7 +49,19 @@ constexpr uint32_t kSpinLimit = 1u << 22;  // default: about 0.4 s of sleeping
 constexpr uint32_t kQueues = 8;            // one per XCD: workgroup b starts on queue b % 8
 
 enum ItemType : uint32_t { ITEM_SMALL = 0, ITEM_SCATTER = 1, ITEM_MARK = 2, ITEM_SCAN = 3, ITEM_RANK = 4,
-                           ITEM_RELABEL = 5 };
+                           ITEM_RELABEL = 5, ITEM_SPLIT = 6, ITEM_FOLD = 7 };
+constexpr uint32_t kStages = 8;
+
+// SPLIT / FOLD geometry: tiles of kTileP positions, vertex buckets of 2^kVB
+// vertices (the FOLD's LDS r), at most kFoldBuckets buckets (the SPLIT's LDS
+// counters), at most kMaxSlices slices per bucket.
+constexpr uint32_t kTileP = 16384;
+constexpr int kVB = 15;
+constexpr uint32_t kBucketV = 1u << kVB;
+constexpr uint32_t kFoldBuckets = 2048;
+constexpr uint32_t kMaxSlices = 4;
+constexpr uint32_t kSentinel = 0xFFFFFFFFu;
+inline uint32_t fold_region(uint32_t nb) { return (kTileP + 3 * nb + 3) & ~3u; }
 
 struct GraphDesc {
     int64_t edge_off;   // first edge
@@ -51,11 +72,17 @@ struct GraphDesc {
     int64_t r_off;      // r (uint32 words) in the workspace, large graphs only
     int64_t w_off;      // bitmap (uint2 words) in the workspace
     int64_t p_off;      // line-aligned private copy of perm, large graphs only
-    uint32_t need[6];   // items per stage (index = ItemType)
+    uint32_t need[kStages];  // items per stage (index = ItemType)
+    // SPLIT / FOLD graphs (fold != 0)
+    uint32_t fold, nb, tiles, region, slices, fold_tiles;
+    int64_t rec_off;    // records: tiles x region words
+    int64_t toff_off;   // segment offsets: tiles x (nb + 1) words
+    int64_t rp_off;     // FOLD minima: slices x n words
 };
 
 struct Item {
     uint32_t type, graph, begin, end;
+    uint32_t bucket, slice;  // FOLD only
 };
 
 struct BatchArgs {
@@ -71,6 +98,9 @@ struct BatchArgs {
     uint32_t *r_pool;     // large-graph r arrays
     uint2 *w_pool;        // bitmaps
     int32_t *p_pool;      // large-graph perm copies read by RELABEL
+    uint32_t *rec_pool;   // SPLIT records
+    uint32_t *toff_pool;  // SPLIT segment offsets
+    uint32_t *rp_pool;    // FOLD minima
     int32_t *flag;
 };
 
@@ -91,6 +121,10 @@ __device__ __forceinline__ uint2 ld_coh2(const uint2 *p) {
 __device__ __forceinline__ void st_coh(uint32_t *p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ void st_coh2(uint32_t *p, uint32_t lo, uint32_t hi) {
+    __hip_atomic_store((uint64_t *)p, (uint64_t)lo | ((uint64_t)hi << 32), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ void drain() {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __builtin_amdgcn_s_waitcnt(0);  // all of this wave's memory operations complete
@@ -100,7 +134,7 @@ __device__ __forceinline__ void drain() {
 // Thread 0 waits until `need` items of (graph, stage) have finished.
 __device__ void wait_stage(const BatchArgs &A, uint32_t g, uint32_t stage, uint32_t need) {
     if (threadIdx.x == 0) {
-        const uint32_t *c = A.done + (size_t)g * 6 + stage;
+        const uint32_t *c = A.done + (size_t)g * kStages + stage;
         uint32_t spins = 0;
         while (ld_coh(c) < need) {
             __builtin_amdgcn_s_sleep(4);
@@ -119,7 +153,7 @@ __device__ void signal_stage(const BatchArgs &A, uint32_t g, uint32_t stage) {
     drain();
     __syncthreads();
     if (threadIdx.x == 0)
-        __hip_atomic_fetch_add(A.done + (size_t)g * 6 + stage, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(A.done + (size_t)g * kStages + stage, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Bitmap prefix popcounts of words [0, nw) by one workgroup.  Words are read
@@ -232,6 +266,118 @@ __device__ void run_small(const BatchArgs &A, const GraphDesc &G, uint32_t *lr, 
     if (bad) flag_range_error(A.flag);
 }
 
+// SPLIT: tile t = positions [t * kTileP, +kTileP) of I ++ J.  Records are
+// staged in `st` (LDS, fold_region(nb) words), bucket counters in `cnt`
+// (2 * kFoldBuckets words).  Records and offsets are written with coherent
+// stores: a FOLD item on another XCD reads them.
+constexpr int kSplitPer = kTileP / kThreads;  // 16
+__device__ bool run_split(const BatchArgs &A, const GraphDesc &G, uint32_t t, uint32_t *st, uint32_t *cnt,
+                          uint32_t *lds) {
+    const uint32_t n = G.n, m = G.m, nb = G.nb;
+    const int32_t *src = A.src + G.edge_off, *dst = A.dst + G.edge_off;
+    uint32_t *hist = cnt, *cur = cnt + kFoldBuckets;
+    const uint32_t p0 = t * kTileP;
+    const uint32_t np = min(kTileP, 2 * m - p0);
+    bool bad = false;
+    for (uint32_t i = threadIdx.x; i < nb; i += kThreads) hist[i] = 0;
+    int32_t v[kSplitPer];
+#pragma unroll
+    for (int j = 0; j < kSplitPer; ++j) {
+        const uint32_t o = j * kThreads + threadIdx.x;
+        const uint32_t p = p0 + min(o, np - 1);
+        v[j] = __builtin_nontemporal_load(p < m ? src + p : dst + (p - m));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kSplitPer; ++j) {
+        const uint32_t o = j * kThreads + threadIdx.x;
+        if (o >= np) {
+            v[j] = -1;
+        } else if ((uint32_t)v[j] >= n) {
+            bad = true;
+            v[j] = -1;
+        } else {
+            atomicAdd(&hist[(uint32_t)v[j] >> kVB], 1u);
+        }
+    }
+    __syncthreads();
+    // segments padded to 4 records; two buckets per thread (nb <= 2 * kThreads)
+    const uint32_t b0 = 2 * threadIdx.x;
+    const uint32_t c0 = b0 < nb ? hist[b0] : 0u, c1 = b0 + 1 < nb ? hist[b0 + 1] : 0u;
+    const uint32_t q0 = (c0 + 3) & ~3u, q1 = (c1 + 3) & ~3u;
+    uint32_t total;
+    const uint32_t s0 = block_exclusive_scan<kThreads>(q0 + q1, OpSum{}, lds, total);
+    uint32_t *toff = A.toff_pool + G.toff_off + (size_t)t * (nb + 1);
+    if (b0 < nb) {
+        cur[b0] = s0;
+        st_coh(toff + b0, s0);
+        for (uint32_t q = c0; q < q0; ++q) st[s0 + q] = kSentinel;
+    }
+    if (b0 + 1 < nb) {
+        cur[b0 + 1] = s0 + q0;
+        st_coh(toff + b0 + 1, s0 + q0);
+        for (uint32_t q = c1; q < q1; ++q) st[s0 + q0 + q] = kSentinel;
+    }
+    if (threadIdx.x == 0) st_coh(toff + nb, total);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kSplitPer; ++j) {
+        if (v[j] >= 0) {
+            const uint32_t o = j * kThreads + threadIdx.x;
+            const uint32_t slot = atomicAdd(&cur[(uint32_t)v[j] >> kVB], 1u);
+            st[slot] = (o << kVB) | ((uint32_t)v[j] & (kBucketV - 1));
+        }
+    }
+    __syncthreads();
+    uint32_t *rec = A.rec_pool + G.rec_off + (size_t)t * G.region;
+    for (uint32_t i = threadIdx.x; i < total / 2; i += kThreads) st_coh2(rec + 2 * i, st[2 * i], st[2 * i + 1]);
+    return bad;
+}
+
+// FOLD: bucket b over tiles [t0, t1) into LDS r (lr), written to slice s.
+constexpr int kFoldU = 4;  // 8-byte loads in flight per lane
+__device__ void run_fold(const BatchArgs &A, const GraphDesc &G, uint32_t b, uint32_t t0, uint32_t t1, uint32_t s,
+                         uint32_t *lr) {
+    const uint32_t n = G.n, nb = G.nb;
+    const uint32_t v0 = b * kBucketV;
+    const uint32_t cntv = min(kBucketV, n - v0);
+    for (uint32_t i = threadIdx.x; i < cntv; i += kThreads) lr[i] = kInf;
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    constexpr uint32_t NW = kThreads / kWave;
+    const uint32_t *toff = A.toff_pool + G.toff_off;
+    const uint32_t *recs = A.rec_pool + G.rec_off;
+    for (uint32_t t = t0 + wave; t < t1; t += NW) {
+        // clamped: after a wait that gave up the offsets may not be this launch's
+        const uint32_t se = min(ld_coh(toff + (size_t)t * (nb + 1) + b + 1), G.region);
+        const uint32_t sb = min(ld_coh(toff + (size_t)t * (nb + 1) + b), se);
+        const uint32_t pb = t * kTileP;
+        const uint32_t *rt = recs + (size_t)t * G.region;
+        for (uint32_t k0 = sb + 2 * lane; k0 < se; k0 += kFoldU * 2 * kWave) {
+            uint2 x[kFoldU];
+#pragma unroll
+            for (int u = 0; u < kFoldU; ++u) {
+                const uint32_t k = k0 + u * 2 * kWave;
+                x[u] = k < se ? ld_coh2((const uint2 *)(rt + k)) : make_uint2(kSentinel, kSentinel);
+            }
+#pragma unroll
+            for (int u = 0; u < kFoldU; ++u) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const uint32_t r = h ? x[u].y : x[u].x;
+                    if (r == kSentinel) continue;
+                    const uint32_t i = r & (kBucketV - 1);
+                    const uint32_t p = pb + (r >> kVB);
+                    if (p < lr[i]) atomicMin(&lr[i], p);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    uint32_t *out = A.rp_pool + G.rp_off + (size_t)s * n + v0;
+    for (uint32_t i = threadIdx.x; i < cntv; i += kThreads) st_coh(out + i, lr[i]);
+}
+
 __global__ __launch_bounds__(kThreads) void k_batch(BatchArgs A) {
     __shared__ uint32_t lr[kSmallMax];
     __shared__ uint32_t stage[kThreads * kScanPer];
@@ -290,12 +436,37 @@ __global__ __launch_bounds__(kThreads) void k_batch(BatchArgs A) {
             signal_stage(A, it.graph, ITEM_SCATTER);
             break;
         }
+        case ITEM_SPLIT:
+            bad = run_split(A, G, it.begin / kTileP, lr, stage, lds);
+            signal_stage(A, it.graph, ITEM_SPLIT);
+            break;
+        case ITEM_FOLD:
+            wait_stage(A, it.graph, ITEM_SPLIT, G.need[ITEM_SPLIT]);
+            run_fold(A, G, it.bucket, it.begin, it.end, it.slice, lr);
+            signal_stage(A, it.graph, ITEM_FOLD);
+            break;
         case ITEM_MARK:
-            wait_stage(A, it.graph, ITEM_SCATTER, G.need[ITEM_SCATTER]);
+            if (G.fold) wait_stage(A, it.graph, ITEM_FOLD, G.need[ITEM_FOLD]);
+            else wait_stage(A, it.graph, ITEM_SCATTER, G.need[ITEM_SCATTER]);
             for (uint32_t v0 = it.begin + threadIdx.x; v0 < it.end; v0 += kThreads * kU) {
                 uint32_t p[kU];
+                if (G.fold) {
+                    // r = the minimum over the FOLD slices, kept for RANK
+                    const uint32_t *rp = A.rp_pool + G.rp_off;
 #pragma unroll
-                for (int j = 0; j < kU; ++j) p[j] = ld_coh(r + min(v0 + j * kThreads, it.end - 1));
+                    for (int j = 0; j < kU; ++j) p[j] = ld_coh(rp + min(v0 + j * kThreads, it.end - 1));
+                    for (uint32_t sl = 1; sl < G.slices; ++sl) {
+#pragma unroll
+                        for (int j = 0; j < kU; ++j)
+                            p[j] = min(p[j], ld_coh(rp + (size_t)sl * n + min(v0 + j * kThreads, it.end - 1)));
+                    }
+#pragma unroll
+                    for (int j = 0; j < kU; ++j)
+                        if (v0 + j * kThreads < it.end) st_coh(r + v0 + j * kThreads, p[j]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < kU; ++j) p[j] = ld_coh(r + min(v0 + j * kThreads, it.end - 1));
+                }
 #pragma unroll
                 for (int j = 0; j < kU; ++j) {
                     const uint32_t v = v0 + j * kThreads;
@@ -409,6 +580,7 @@ struct HostPlan {
     std::vector<Item> items;
     uint32_t qstart[kQueues + 1] = {};
     uint64_t r_words = 0, w_words = 0, p_words = 0;
+    uint64_t rec_words = 0, toff_words = 0, rp_words = 0;
     uint32_t n_small = 0;
 };
 
@@ -420,6 +592,7 @@ boba_status build_host_plan(int32_t G, const int64_t *eo, const int64_t *vo, boo
     const uint32_t vertex_tile = tu && tu->vertex_tile > 0 ? (uint32_t)tu->vertex_tile : 65536u;
     const uint32_t relabel_tile = tu && tu->relabel_tile > 0 ? (uint32_t)tu->relabel_tile : 262144u;
     const uint32_t nq = tu && tu->queues > 0 ? (uint32_t)std::min<int32_t>(tu->queues, (int32_t)kQueues) : kQueues;
+    const bool atomic_scatter = tu && tu->scatter_atomic > 0;
     H.graphs.resize(G);
     std::vector<int32_t> big, small;
     for (int32_t g = 0; g < G; ++g) {
@@ -446,6 +619,25 @@ boba_status build_host_plan(int32_t G, const int64_t *eo, const int64_t *vo, boo
             H.r_words += (uint64_t)n;
             D.p_off = (int64_t)H.p_words;
             H.p_words += ((uint64_t)n + 63) & ~63ull;  // 256-byte lines of its own
+            const uint32_t nb = (uint32_t)ceil_div((uint64_t)n, kBucketV);
+            if (!atomic_scatter && m > 0 && nb <= kFoldBuckets) {
+                D.fold = 1;
+                D.nb = nb;
+                D.tiles = (uint32_t)ceil_div(2 * (uint64_t)m, kTileP);
+                D.region = fold_region(nb);
+                // slices of about scatter_tile records per (bucket, slice)
+                uint64_t sl = ceil_div(2 * (uint64_t)m, (uint64_t)nb * scatter_tile);
+                sl = std::min<uint64_t>({std::max<uint64_t>(sl, 1), kMaxSlices, D.tiles});
+                const uint32_t ft = (uint32_t)ceil_div(D.tiles, sl);
+                D.slices = (uint32_t)ceil_div(D.tiles, ft);
+                D.fold_tiles = ft;
+                D.rec_off = (int64_t)H.rec_words;
+                H.rec_words += (uint64_t)D.tiles * D.region;
+                D.toff_off = (int64_t)H.toff_words;
+                H.toff_words += (uint64_t)D.tiles * (nb + 1);
+                D.rp_off = (int64_t)H.rp_words;
+                H.rp_words += (uint64_t)D.slices * (uint64_t)n;
+            }
             big.push_back(g);
         }
     }
@@ -472,8 +664,19 @@ boba_status build_host_plan(int32_t G, const int64_t *eo, const int64_t *vo, boo
     };
     for (uint32_t q = 0; q < kQueues; ++q) {
         H.qstart[q] = (uint32_t)H.items.size();
-        for (int32_t g : qbig[q]) tiles(ITEM_SCATTER, g, 2ull * H.graphs[g].m, scatter_tile);
+        for (int32_t g : qbig[q]) {
+            if (H.graphs[g].fold) tiles(ITEM_SPLIT, g, 2ull * H.graphs[g].m, kTileP);
+            else tiles(ITEM_SCATTER, g, 2ull * H.graphs[g].m, scatter_tile);
+        }
         for (int32_t g : qsmall[q]) H.items.push_back(Item{ITEM_SMALL, (uint32_t)g, 0, 0});
+        for (int32_t g : qbig[q]) {
+            GraphDesc &D = H.graphs[g];
+            if (!D.fold) continue;
+            for (uint32_t b = 0; b < D.nb; ++b)
+                for (uint32_t sl = 0; sl < D.slices; ++sl)
+                    H.items.push_back(Item{ITEM_FOLD, (uint32_t)g, sl * D.fold_tiles, std::min(D.tiles, (sl + 1) * D.fold_tiles), b, sl});
+            D.need[ITEM_FOLD] = D.nb * D.slices;
+        }
         for (int32_t g : qbig[q]) tiles(ITEM_MARK, g, H.graphs[g].n, vertex_tile);
         for (int32_t g : qbig[q]) tiles(ITEM_SCAN, g, 1, 1);
         for (int32_t g : qbig[q]) tiles(ITEM_RANK, g, H.graphs[g].n, vertex_tile);
@@ -492,6 +695,7 @@ struct BatchLayout {
     uint32_t *r;
     uint2 *w;
     int32_t *p;
+    uint32_t *rec, *toff, *rp;
     size_t bytes;
 };
 
@@ -500,10 +704,13 @@ BatchLayout batch_layout(void *ws, const HostPlan &H) {
     Carver c(ws);
     L.graphs = c.take<GraphDesc>(H.graphs.size());
     L.items = c.take<Item>(H.items.size());
-    L.queue_and_done = c.take<uint32_t>(kQueues + 1 + 6 * H.graphs.size());
+    L.queue_and_done = c.take<uint32_t>(kQueues + 1 + kStages * H.graphs.size());
     L.r = c.take<uint32_t>(H.r_words);
     L.w = c.take<uint2>(H.w_words);
     L.p = c.take<int32_t>(H.p_words);
+    L.rec = c.take<uint32_t>(H.rec_words);
+    L.toff = c.take<uint32_t>(H.toff_words);
+    L.rp = c.take<uint32_t>(H.rp_words);
     L.bytes = c.bytes();
     return L;
 }
@@ -571,6 +778,9 @@ extern "C" boba_status boba_batch_plan_create(int32_t G, const int64_t *h_edge_o
     A.r_pool = L.r;
     A.w_pool = L.w;
     A.p_pool = L.p;
+    A.rec_pool = L.rec;
+    A.toff_pool = L.toff;
+    A.rp_pool = L.rp;
     A.flag = flag;
     A.spin_limit = tuning && tuning->spin_limit > 0 ? (uint32_t)tuning->spin_limit : kSpinLimit;
 
@@ -581,7 +791,7 @@ extern "C" boba_status boba_batch_plan_create(int32_t G, const int64_t *h_edge_o
     hipGraph_t graph = nullptr;
     e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        const uint32_t nc = kQueues + 1 + 6 * (uint32_t)G;
+        const uint32_t nc = kQueues + 1 + kStages * (uint32_t)G;
         hipLaunchKernelGGL(k_batch_init, dim3(grid_for(std::max<uint64_t>({H.r_words, H.w_words, (uint64_t)nc}), 1024)),
                            dim3(256), 0, cap, L.r, H.r_words, L.w, H.w_words, L.queue_and_done, nc);
         if (n_items > 0)

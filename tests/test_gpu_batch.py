@@ -110,6 +110,52 @@ def test_every_item_in_one_queue_is_run_by_all_xcds(batch):
         plan.destroy()
 
 
+def test_atomic_scatter_path(batch):
+    # large graphs through device-wide atomic minima (the path of graphs with
+    # more than 2^26 vertices) instead of SPLIT + FOLD
+    eo, vo, src, dst = batch
+    plan = boba.BatchPlan(eo, vo, dev(src), dev(dst), tuning=boba.boba_tuning(0, 0, 0, 0, 0, 0, 1))
+    for rep in range(2):
+        plan.launch()
+        check_against_oracle(eo, vo, src, dst, host(plan.perm), host(plan.order), host(plan.src_out),
+                             host(plan.dst_out))
+    assert boba.boba_check_device_error() == boba.BOBA_OK
+    plan.destroy()
+
+
+@pytest.mark.parametrize("scatter_tile", [0, 4096])
+def test_many_buckets_and_slices(scatter_tile):
+    # SPLIT / FOLD at the bucket limit (2^26 vertices: 2048 buckets of 2^15),
+    # a 129-bucket graph, a graph whose edges all hit one bucket, and small
+    # members; scatter_tile 4096 gives the two smaller large graphs four slices
+    rng = np.random.default_rng(41)
+    graphs, ns = [], []
+    n = 1 << 26
+    graphs.append((rng.integers(0, n, 1 << 20, dtype=np.int32), rng.integers(0, n, 1 << 20, dtype=np.int32)))
+    ns.append(n)
+    n = (1 << 22) + 5
+    g = graphgen.small_workload("rmat", n, 3000001, 42)
+    graphs.append((g.src, g.dst))
+    ns.append(n)
+    n = 200003
+    graphs.append((rng.integers(65536, 98304, 500001, dtype=np.int32), rng.integers(65536, 98304, 500001, dtype=np.int32)))
+    ns.append(n)
+    graphs.append((np.array([2, 0, 1], np.int32), np.array([1, 1, 0], np.int32)))
+    ns.append(3)
+    m = np.array([a.size for a, _ in graphs], np.int64)
+    eo = np.concatenate([[0], np.cumsum(m)]).astype(np.int64)
+    vo = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+    src = np.concatenate([a for a, _ in graphs])
+    dst = np.concatenate([b for _, b in graphs])
+    print(f"batch: n={int(vo[-1])} m={int(eo[-1])} scatter_tile={scatter_tile}", flush=True)
+    plan = boba.BatchPlan(eo, vo, dev(src), dev(dst), tuning=boba.boba_tuning(0, scatter_tile, 0, 0))
+    plan.launch()
+    check_against_oracle(eo, vo, src, dst, host(plan.perm), host(plan.order), host(plan.src_out),
+                         host(plan.dst_out))
+    assert boba.boba_check_device_error() == boba.BOBA_OK
+    plan.destroy()
+
+
 def test_a_wait_that_gives_up_is_reported_as_a_timeout():
     # a spin limit of one sleep: waits for other workgroups' stages give up
     # almost at once (every kernel still runs to its end); the launch then
