@@ -266,6 +266,89 @@ __device__ void run_small(const BatchArgs &A, const GraphDesc &G, uint32_t *lr, 
     if (bad) flag_range_error(A.flag);
 }
 
+// Exclusive sum over the workgroup of 64-bit values (lds: kThreads / kWave
+// uint64); two barriers.
+__device__ uint64_t block_exclusive_sum64(uint64_t x, uint64_t *lds, uint64_t &total) {
+    constexpr int NW = kThreads / kWave;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    uint64_t incl = x;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint64_t y = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += y;
+    }
+    if (lane == kWave - 1) lds[wave] = incl;
+    __syncthreads();
+    uint64_t before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const uint64_t s = lds[w];
+        if (w < wave) before += s;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return before + incl - x;
+}
+
+// SPLIT of a graph with at most kFewBuckets buckets (every graph of up to
+// 2^18 vertices): per-thread counts in 16-bit fields of two registers and one
+// packed scan give every element its slot, with no LDS atomics (with so few
+// buckets, per-element atomics on the counters serialize).  Tile counts fit
+// in 16 bits (kTileP = 2^14).
+constexpr uint32_t kFewBuckets = 8;
+__device__ bool split_few(const BatchArgs &A, const GraphDesc &G, uint32_t t, const int32_t (&v)[kTileP / kThreads],
+                          uint32_t *st) {
+    const uint32_t nb = G.nb;
+    uint64_t c[2] = {0, 0};
+#pragma unroll
+    for (int j = 0; j < (int)(kTileP / kThreads); ++j) {
+        if (v[j] < 0) continue;
+        const uint32_t b = (uint32_t)v[j] >> kVB;
+        const uint64_t inc = 1ull << (16 * (b & 3));
+        if (b < 4) c[0] += inc;
+        else c[1] += inc;
+    }
+    uint64_t tot[2];
+    __shared__ uint64_t scan64[kThreads / kWave];
+    uint64_t e[2];
+    e[0] = block_exclusive_sum64(c[0], scan64, tot[0]);
+    e[1] = block_exclusive_sum64(c[1], scan64, tot[1]);
+    // bucket b's segment starts at fstart[b], padded to 4 records;
+    // fstart[kFewBuckets] = the tile's total
+    __shared__ uint32_t fstart[kFewBuckets + 1];
+    if (threadIdx.x == 0) {
+        uint32_t total = 0;
+        for (uint32_t b = 0; b < kFewBuckets; ++b) {
+            const uint32_t cb = b < nb ? (uint32_t)(tot[b >> 2] >> (16 * (b & 3))) & 0xFFFFu : 0u;
+            fstart[b] = total;
+            for (uint32_t q = cb; q < ((cb + 3) & ~3u); ++q) st[total + q] = kSentinel;
+            total += (cb + 3) & ~3u;
+        }
+        fstart[kFewBuckets] = total;
+    }
+    __syncthreads();
+    uint32_t *toff = A.toff_pool + G.toff_off + (size_t)t * (nb + 1);
+    if (threadIdx.x <= nb) st_coh(toff + threadIdx.x, fstart[threadIdx.x < nb ? threadIdx.x : kFewBuckets]);
+#pragma unroll
+    for (int j = 0; j < (int)(kTileP / kThreads); ++j) {
+        if (v[j] < 0) continue;
+        const uint32_t b = (uint32_t)v[j] >> kVB;
+        const uint32_t sh = 16 * (b & 3);
+        const uint64_t eb = b < 4 ? e[0] : e[1];
+        const uint32_t slot = fstart[b] + ((uint32_t)(eb >> sh) & 0xFFFFu);
+        if (b < 4) e[0] = eb + (1ull << sh);
+        else e[1] = eb + (1ull << sh);
+        const uint32_t o = j * kThreads + threadIdx.x;
+        st[slot] = (o << kVB) | ((uint32_t)v[j] & (kBucketV - 1));
+    }
+    const uint32_t total = fstart[kFewBuckets];
+    __syncthreads();
+    uint32_t *rec = A.rec_pool + G.rec_off + (size_t)t * G.region;
+    for (uint32_t i = threadIdx.x; i < total / 2; i += kThreads) st_coh2(rec + 2 * i, st[2 * i], st[2 * i + 1]);
+    return false;
+}
+
 // SPLIT: tile t = positions [t * kTileP, +kTileP) of I ++ J.  Records are
 // staged in `st` (LDS, fold_region(nb) words), bucket counters in `cnt`
 // (2 * kFoldBuckets words).  Records and offsets are written with coherent
@@ -296,10 +379,12 @@ __device__ bool run_split(const BatchArgs &A, const GraphDesc &G, uint32_t t, ui
         } else if ((uint32_t)v[j] >= n) {
             bad = true;
             v[j] = -1;
-        } else {
-            atomicAdd(&hist[(uint32_t)v[j] >> kVB], 1u);
         }
     }
+    if (nb <= kFewBuckets) return split_few(A, G, t, v, st) || bad;
+#pragma unroll
+    for (int j = 0; j < kSplitPer; ++j)
+        if (v[j] >= 0) atomicAdd(&hist[(uint32_t)v[j] >> kVB], 1u);
     __syncthreads();
     // segments padded to 4 records; two buckets per thread (nb <= 2 * kThreads)
     const uint32_t b0 = 2 * threadIdx.x;
