@@ -863,6 +863,20 @@ constexpr uint32_t kPermChunk = 1024;  // key blocks rank_perm takes at a time (
 constexpr uint32_t kMaxKeyBits = 18;                            // rank_block LDS <= 48 KB
 constexpr uint32_t kTargetKeyBlocks = 4096;                    // bounds a key block's entries
 constexpr uint32_t kMaxKeyBlocks = 1u << (32 - kMaxKeyBits);    // 2m < 2^32
+// Key blocks: the first nsmall blocks span 2^ks positions each, the rest
+// 2^kbits.  First occurrences are densest at the start of S, where a block of
+// 2^kbits positions can hold that many keys for one workgroup to rank (at
+// RMAT-24 the first 2^17-position block took 0.14 ms, alone at the end of
+// rank_block), so the start is cut 4x finer.
+struct KeyBlocks {
+    uint32_t kbits, ks, nsmall;
+    __host__ __device__ uint32_t lead() const { return nsmall << ks; }
+    __device__ uint32_t block(uint32_t p) const { return p < lead() ? p >> ks : nsmall + ((p - lead()) >> kbits); }
+    __device__ uint32_t base(uint32_t b) const { return b < nsmall ? b << ks : lead() + ((b - nsmall) << kbits); }
+    __device__ uint32_t bits(uint32_t b) const { return b < nsmall ? ks : kbits; }
+};
+constexpr uint32_t kSmallKeyBlocks = 64;
+constexpr uint32_t kMinSmallKeyBits = 12;
 constexpr uint32_t kMinRankBits = 10;                           // a rank bucket spans at least kMinThreads vertices
 constexpr uint64_t kTargetRankBuckets = 512;
 constexpr uint64_t kMaxRankTable = 1u << 21;
@@ -879,7 +893,7 @@ __device__ __forceinline__ uint32_t merged_r(const uint32_t *__restrict__ rpart,
 // the scan of the transposed counts leaves the total.
 __global__ __launch_bounds__(kMinThreads) void k_rank_count(uint32_t *__restrict__ rpart, uint32_t slices,
                                                             uint32_t n, uint32_t nb, uint32_t rbits, uint32_t nblk,
-                                                            uint32_t kbits, uint32_t *__restrict__ cnt_b,
+                                                            KeyBlocks kb, uint32_t *__restrict__ cnt_b,
                                                             uint32_t *__restrict__ cnt) {
     __shared__ uint32_t h[kMaxKeyBlocks + 1];
     const uint32_t b = blockIdx.x;
@@ -898,7 +912,7 @@ __global__ __launch_bounds__(kMinThreads) void k_rank_count(uint32_t *__restrict
         // isolated vertices are common (about 38% in RMAT): one atomic per wave
         const uint64_t bal = __ballot(iso);
         if (iso && lane == (uint32_t)(__ffsll((long long)bal) - 1)) atomicAdd(&h[nblk], (uint32_t)__popcll(bal));
-        if (i < cntv && !iso) atomicAdd(&h[p >> kbits], 1u);
+        if (i < cntv && !iso) atomicAdd(&h[kb.block(p)], 1u);
     }
     __syncthreads();
     for (uint32_t k = threadIdx.x; k <= nblk; k += kMinThreads) cnt_b[(size_t)b * (nblk + 1) + k] = h[k];
@@ -906,7 +920,7 @@ __global__ __launch_bounds__(kMinThreads) void k_rank_count(uint32_t *__restrict
 
 // r: the merged minima (slice 0 after rank_count)
 __global__ __launch_bounds__(kMinThreads) void k_rank_scatter(const uint32_t *__restrict__ r, uint32_t n,
-                                                              uint32_t rbits, uint32_t nblk, uint32_t kbits,
+                                                              uint32_t rbits, uint32_t nblk, KeyBlocks kb,
                                                               const uint32_t *__restrict__ off_b, uint2 *__restrict__ E) {
     __shared__ uint32_t cur[kMaxKeyBlocks];
     const uint32_t b = blockIdx.x;
@@ -925,7 +939,7 @@ __global__ __launch_bounds__(kMinThreads) void k_rank_scatter(const uint32_t *__
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (p[u] != kInf) {
-                const uint32_t slot = atomicAdd(&cur[p[u] >> kbits], 1u);
+                const uint32_t slot = atomicAdd(&cur[kb.block(p[u])], 1u);
                 E[slot] = make_uint2(p[u], v0 + i0 + u * kMinThreads);
             }
         }
@@ -944,10 +958,12 @@ inline size_t rank_block_lds(uint32_t kbits) {
 
 __global__ __launch_bounds__(kRankThreads) void k_rank_block(uint2 *__restrict__ E,
                                                              const uint32_t *__restrict__ off, uint32_t nb,
-                                                             uint32_t kbits, int32_t *__restrict__ order) {
+                                                             KeyBlocks kb, int32_t *__restrict__ order) {
     extern __shared__ __align__(16) uint32_t dyn[];
+    // LDS sized for a regular block; a small one uses the front of each array
+    const uint32_t kbits = kb.bits(blockIdx.x);
     const uint32_t nwords = 1u << (kbits - 5);
-    const uint32_t ngroups = nwords / kWave;  // 16 .. 256
+    const uint32_t ngroups = nwords / kWave;  // 2 .. 256
     uint32_t *bits = dyn;
     uint16_t *pre = (uint16_t *)(dyn + nwords);      // exclusive popcount within a 64-word group
     uint32_t *gbase = dyn + nwords + nwords / 2;     // exclusive popcount of the groups
@@ -960,7 +976,7 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_block(uint2 *__restrict__
     __syncthreads();
     const uint32_t e0 = off[(size_t)blk * nb];
     const uint32_t e1 = off[(size_t)(blk + 1) * nb];
-    const uint32_t base = blk << kbits;
+    const uint32_t base = kb.base(blk);
     constexpr int U = 8;  // entries in flight per thread
     // a block of at most U * kRankThreads entries (nearly all) stays in
     // registers between setting the bits and ranking
@@ -1142,7 +1158,8 @@ struct ReorderPlan {
     bool small;     // one workgroup, one launch (small_graph), unless BOBA_FLAG_FORCE_GENERAL
     bool bucketed;
     uint32_t nb, tiles_half, nt, region, slices, tps;
-    uint32_t kbits, nblk;  // key blocks of the bucketed ranking
+    KeyBlocks kb;          // key blocks of the bucketed ranking
+    uint32_t nblk;
     uint32_t rbits, nbr;   // rank buckets: 2^rbits vertices each, nbr of them
 };
 
@@ -1170,9 +1187,24 @@ ReorderPlan reorder_plan(int64_t n, int64_t m) {
         // a graph hold most first occurrences, and a small block bounds the
         // work of the workgroup that ranks it
         const uint64_t keys = 2 * (uint64_t)m;
-        P.kbits = kMinKeyBits;
-        while (P.kbits < kMaxKeyBits && (keys >> P.kbits) > kTargetKeyBlocks) ++P.kbits;
-        P.nblk = (uint32_t)((keys + (1ull << P.kbits) - 1) >> P.kbits);
+        uint32_t kbits = kMinKeyBits;
+        while (kbits < kMaxKeyBits && (keys >> kbits) > kTargetKeyBlocks) ++kbits;
+        // the leading blocks 4x finer (at most kSmallKeyBlocks of them)
+        const uint32_t ks = kbits - 2 > kMinSmallKeyBits ? kbits - 2 : kMinSmallKeyBits;
+        const uint64_t lead_max = (uint64_t)kSmallKeyBlocks << ks;
+        uint64_t nblk;
+        if (keys <= lead_max) {
+            P.kb = KeyBlocks{kbits, ks, (uint32_t)ceil_div(keys, 1ull << ks)};
+            nblk = P.kb.nsmall;
+        } else {
+            P.kb = KeyBlocks{kbits, ks, kSmallKeyBlocks};
+            nblk = kSmallKeyBlocks + ceil_div(keys - lead_max, 1ull << kbits);
+        }
+        if (nblk > kMaxKeyBlocks) {  // only near 2m = 2^32: regular blocks throughout
+            P.kb = KeyBlocks{kbits, kbits, 0};
+            nblk = ceil_div(keys, 1ull << kbits);
+        }
+        P.nblk = (uint32_t)nblk;
         // rank buckets: narrower than the split's until there are about 512
         // (two 1024-thread workgroups per CU), while the count table
         // (key blocks + 1) x rank buckets stays within 2^21 words
@@ -1283,7 +1315,7 @@ boba_status reorder_run(const int32_t *src, const int32_t *dst, uint32_t um, uin
                         P.tps, min_batch(P), un, inter ? 1u : um, inter ? 2u : 1u, L.r);
         const uint32_t kcols = P.nblk + 1;  // key blocks and the tail block
         BOBA_LAUNCH("rank_count", k_rank_count, dim3(P.nbr), dim3(kMinThreads), stream, L.r, P.slices, un, P.nbr,
-                    P.rbits, P.nblk, P.kbits, L.cnt_b, L.cnt);
+                    P.rbits, P.nblk, P.kb, L.cnt_b, L.cnt);
         // bucket-major counts -> block-major, scanned in place -> bucket-major offsets
         BOBA_LAUNCH("rank_transpose", k_transpose, dim3(ceil_div(kcols, 32), ceil_div(P.nbr, 32)), dim3(256), stream,
                     (const uint32_t *)L.cnt_b, P.nbr, kcols, L.cnt);
@@ -1293,12 +1325,12 @@ boba_status reorder_run(const int32_t *src, const int32_t *dst, uint32_t um, uin
         BOBA_LAUNCH("rank_transpose", k_transpose, dim3(ceil_div(P.nbr, 32), ceil_div(kcols, 32)), dim3(256), stream,
                     (const uint32_t *)L.cnt, kcols, P.nbr, L.off_b);
         BOBA_LAUNCH("rank_scatter", k_rank_scatter, dim3(P.nbr), dim3(kMinThreads), stream, (const uint32_t *)L.r,
-                    un, P.rbits, P.nblk, P.kbits, (const uint32_t *)L.off_b, L.E);
+                    un, P.rbits, P.nblk, P.kb, (const uint32_t *)L.off_b, L.E);
         {
-            const size_t lds = rank_block_lds(P.kbits);
+            const size_t lds = rank_block_lds(P.kb.kbits);
             const int tok = timing_begin("rank_block", stream);
             hipLaunchKernelGGL(k_rank_block, dim3(P.nblk), dim3(kRankThreads), lds, stream, L.E,
-                               (const uint32_t *)L.cnt, P.nbr, P.kbits, order);
+                               (const uint32_t *)L.cnt, P.nbr, P.kb, order);
             timing_end(tok, stream);
             if (boba_status e = check_launch("rank_block")) return e;
         }

@@ -301,9 +301,11 @@ def test_fused_reorder_relabel_in_place_and_unaligned(general):
 
 
 # The bucketed ranking groups first positions into key blocks of 2^15 .. 2^18
-# positions (about 4096 blocks); these sizes give one block, a few, 1025, 4097
-# (2^15 positions each) and 2051 (2^16), with ragged last blocks and buckets.
-# RMAT-24 (2^17-position blocks) is in the full-scale tests.
+# positions (about 4096 blocks), the first 64 of them 4x finer (at least 2^12
+# positions); these sizes give one small block, 33 small blocks, and 64 small
+# blocks followed by 1009, 4081 (2^15 positions each) and 2035 (2^16) regular
+# ones, with ragged last blocks and buckets.  RMAT-24 (2^15 / 2^17) is in the
+# full-scale tests.
 @pytest.mark.parametrize("n,m", [
     (5000, 7),
     (70001, (1 << 17) + 5),
