@@ -20,11 +20,13 @@ from . import boba
 
 GRID = {
     "small_max_n": [8192, 16384, 32768],
-    "scatter_tile": [16384, 65536, 262144],
+    # records per (vertex bucket, slice) item: 4M gives one slice per bucket
+    # for graphs of up to 2^24 edges, 64K four
+    "scatter_tile": [65536, 262144, 1048576, 4194304],
     "vertex_tile": [16384, 65536],
     "relabel_tile": [16384, 65536, 262144],
 }
-DEFAULT = {"small_max_n": 32768, "scatter_tile": 16384, "vertex_tile": 16384, "relabel_tile": 16384}
+DEFAULT = {"small_max_n": 32768, "scatter_tile": 262144, "vertex_tile": 16384, "relabel_tile": 16384}
 
 
 def cache_path() -> str:
