@@ -777,8 +777,22 @@ def bench_batch(batch, reps, dev):
             "per_graph_hipgraph_ms": graph_ms, "speedup": per_graph_ms / batched_ms,
             "speedup_vs_hipgraph": graph_ms / batched_ms, "edges_per_s": m_tot / (batched_ms * 1e-3),
             "identical_to_per_graph": same and same_graph, "plan": info, "tuning": best,
+            "roofline": batch_roofline(m_tot, int(vo[-1]), batched_ms, G),
             "includes": "reorder + relabel",
             "per_graph_call": "boba_reorder_relabel per graph; also captured into one hipGraph and replayed"}
+
+
+def batch_roofline(m, n, ms, graphs):
+    """The batched kernel against HBM peak on the method's bytes for reorder +
+    relabel of every graph (16m + 16n: I and J read, r written and read,
+    perm and order written, I' and J' written), with the rocprofv3 traffic of
+    k_batch when its summary was taken on the current sources."""
+    alg = 16 * m + 16 * n
+    achieved = alg / (ms * 1e-3) / 1e9
+    traffic = pmc_traffic("batch", f"batch{graphs}", 1)
+    return {"bound": "hbm", "kernel": "batch", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "alg_bytes_per_launch": alg, "traffic": traffic,
+            "traffic_over_alg_bytes": traffic / alg if traffic else None}
 
 
 def prepare_selector_graphs(count):
