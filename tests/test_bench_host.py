@@ -89,3 +89,12 @@ def test_tuner_cache_key_and_struct(monkeypatch, tmp_path):
     assert (st.small_max_n, st.scatter_tile) == (tune.DEFAULT["small_max_n"], tune.DEFAULT["scatter_tile"])
     for name, values in tune.GRID.items():
         assert tune.DEFAULT[name] in values, name
+
+
+def test_batch_roofline_on_the_method_bytes():
+    import bench
+    r = bench.batch_roofline(m=1000, n=100, ms=1e-3, graphs=3)
+    assert r["alg_bytes_per_launch"] == 16 * 1000 + 16 * 100
+    assert abs(r["achieved"] - 17600 / 1e-6 / 1e9) < 1e-9
+    assert abs(r["frac"] - r["achieved"] / bench.HBM_PEAK_GBS) < 1e-12
+    assert r["traffic"] is None  # no summary for a 3-graph batch

@@ -156,6 +156,28 @@ def test_many_buckets_and_slices(scatter_tile):
     plan.destroy()
 
 
+def test_split_bucket_count_boundaries():
+    # SPLIT's packed-count path takes graphs of at most 8 buckets: 1 bucket
+    # (a graph above small_max_n = 1000 but below 2^15 vertices), 8 (2^18
+    # vertices) and 9 (2^18 + 1), next to the per-element path
+    rng = np.random.default_rng(43)
+    ns = [2000, 1 << 18, (1 << 18) + 1, 5000]
+    ms = [30001, 1000003, 999999, 77]
+    graphs = [(rng.integers(0, n, m, dtype=np.int32), rng.integers(0, n, m, dtype=np.int32)) for n, m in zip(ns, ms)]
+    m = np.array(ms, np.int64)
+    eo = np.concatenate([[0], np.cumsum(m)]).astype(np.int64)
+    vo = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+    src = np.concatenate([a for a, _ in graphs])
+    dst = np.concatenate([b for _, b in graphs])
+    for atomic in (0, 1):
+        plan = boba.BatchPlan(eo, vo, dev(src), dev(dst), tuning=boba.boba_tuning(1000, 0, 0, 0, 0, 0, atomic))
+        plan.launch()
+        check_against_oracle(eo, vo, src, dst, host(plan.perm), host(plan.order), host(plan.src_out),
+                             host(plan.dst_out))
+        assert boba.boba_check_device_error() == boba.BOBA_OK
+        plan.destroy()
+
+
 def test_a_wait_that_gives_up_is_reported_as_a_timeout():
     # a spin limit of one sleep: waits for other workgroups' stages give up
     # almost at once (every kernel still runs to its end); the launch then
