@@ -6,7 +6,7 @@ the library's own kernels) picks, per graph, between keeping the input order
 and BOBA.  The graphs: small ones below the gate (reordering costs more than
 the 20 SpMVs win back), two large random geometric graphs above it (BOBA wins
 back several times its cost) and two RMAT graphs above it (reordering them
-costs about 20% more than it wins back).  The selector's total time,
+costs more than it wins back).  The selector's total time,
 including its own feature and inference time, must beat both fixed policies:
 always reordering (the method alone) and never reordering.  On the graphs
 above the gate it must also beat the gate alone (always reordering there):
