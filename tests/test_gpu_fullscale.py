@@ -71,6 +71,25 @@ def test_rmat24_fused_reorder_relabel_as_timed(rmat24):
 
 
 @pytest.mark.timeout(600)
+def test_rmat24_interleaved_flattening(rmat24):
+    # S = I(0) J(0) I(1) J(1) ... (the flattening of Fig. 1), through the
+    # reorder and the fused reorder+relabel, every element against the oracle
+    g = rmat24
+    s, d = dev(g.src), dev(g.dst)
+    fl = boba.BOBA_FLAG_INTERLEAVED
+    perm, order = boba.boba_reorder(s, d, g.n, flags=fl)
+    p_ref, o_ref = oracle.boba(g.src, g.dst, g.n, interleaved=True)
+    assert np.array_equal(host(perm), p_ref)
+    assert np.array_equal(host(order), o_ref)
+    del perm, order
+    fp, _, fs, fd = boba.boba_reorder_relabel(s, d, g.n, flags=fl, with_order=False)
+    assert np.array_equal(host(fp), p_ref)
+    s2_ref, d2_ref = oracle.relabel(g.src, g.dst, p_ref)
+    assert np.array_equal(host(fs), s2_ref) and np.array_equal(host(fd), d2_ref)
+    assert boba.boba_check_device_error() == boba.BOBA_OK
+
+
+@pytest.mark.timeout(600)
 def test_grid4096_full_path():
     # the mesh workload (Fig. 2's regime) through reorder, relabel, CSR and
     # FP32 SpMV, every array against the oracle, SpMV against FP64
